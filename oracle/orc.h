@@ -1,0 +1,112 @@
+/*
+ * orc.h -- FP64 CPU oracle for DeepInverse (Mousavi & Baraniuk, arXiv 1701.03891).
+ *
+ * TEST INFRASTRUCTURE ONLY.  Only the test-suite, the smoke check and the
+ * benchmark's CPU-baseline leg may load this library.  It shares no code,
+ * header, table or helper with the GPU library and must never be used as a
+ * fallback for it.
+ *
+ * Everything is plain double precision, written as the definitions in the
+ * paper state them, with no blocking or reordering:
+ *   - measurement  y = Phi x                                   (Sec. 1)
+ *   - signal proxy x~ = Phi^T y, by a fixed fully connected layer (Sec. 4)
+ *   - conv layer   S(ReLU(W * x + b)), full 2-D correlation over the
+ *                  zero-padded input, bias over the full-size grid, ReLU,
+ *                  crop S of the padding borders                 (Sec. 4, Eq. 1)
+ *   - loss         L = (1/l) sum_i ||M(y_i) - x_i||^2            (Sec. 4)
+ *   - gradients by backpropagation of L                          (Sec. 4)
+ *   - Adam update (Kingma & Ba), PSNR (Sec. 5 footnote), success indicator
+ *     phi = I(||xhat - x||^2 / ||x||^2 <= 0.1)                    (Sec. 5)
+ *   - ISTA in the orthonormal 2-D DCT basis: the sparsity-regularised convex
+ *     recovery that Sec. 1 cites, as the classical reference.
+ *
+ * Layouts: images are row-major n1 x n2 (pixel p = i*n2 + j); feature maps
+ * are planar [C][n1][n2] per image; weights are [Cout][Cin][k][k]; "full"
+ * biases are [Cout][n1+k-1][n2+k-1] (the size Eq. 1 gives them), channel
+ * biases are [Cout].  Batches are the outermost index.
+ *
+ * Parity unpinned: none of these functions -- every one is pinned by a
+ * closed form, an invariant, a library routine or brute force in the
+ * test-suite's oracle tests.
+ */
+#ifndef ORC_H
+#define ORC_H
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* Network description: L conv layers, channels C[0..L], odd filter sizes k[0..L-1]. */
+typedef struct {
+  int n1, n2;   /* image rows and columns, N = n1*n2 */
+  int M;        /* number of measurements */
+  int L;        /* number of conv layers */
+  int C[9];     /* channel counts, C[0] = C[L] = 1 */
+  int k[8];     /* filter sizes (odd) */
+  int bias_full;/* 1: per-pixel bias over the full (n+k-1) grid, 0: per channel */
+  int relu_last;/* 1: ReLU on the last layer too */
+} orc_net;
+
+/* y[b][m] = sum_n phi[m][n] x[b][n]                                    (Sec. 1) */
+void orc_measure(const double *phi, const double *x, double *y, int B, int M, int N);
+
+/* xt[b][p] = sum_m wfc[p][m] y[b][m]; wfc = Phi^T, shape [N][M]         (Sec. 4) */
+void orc_proxy(const double *wfc, const double *y, double *xt, int B, int M, int N);
+
+/* One conv layer of Eq. (1) on ONE image.  in [Cin][n1][n2], w [Cout][Cin][k][k],
+ * bias [Cout][n1+k-1][n2+k-1] (bias_full) or [Cout].  zfull (nullable) receives
+ * the full-size pre-activation [Cout][n1+k-1][n2+k-1]; out [Cout][n1][n2]. */
+void orc_conv_layer(const double *in, int Cin, int n1, int n2, const double *w, int Cout,
+                    int k, const double *bias, int bias_full, int relu, double *zfull,
+                    double *out);
+
+/* Bytes of doubles needed per image to keep all activations (for orc_forward's acts). */
+long orc_acts_per_image(const orc_net *net);
+
+/* Forward map xhat = M(y, Omega) for a batch.  w[l], b[l] as in orc_conv_layer.
+ * acts (nullable): per image, orc_acts_per_image doubles holding a_0..a_L and
+ * the full-size pre-activations z_1..z_L, in that order. */
+void orc_forward(const orc_net *net, const double *wfc, const double *const *w,
+                 const double *const *b, const double *y, int B, double *xhat, double *acts);
+
+/* L = (1/B) sum_b ||xhat_b - x_b||^2; g (nullable) = dL/dxhat = (2/B)(xhat - x). */
+double orc_loss(const double *xhat, const double *x, int B, int N, double *g);
+
+/* Loss and gradients of L with respect to every parameter, by backpropagation.
+ * gw[l], gb[l] have the shapes of w[l], b[l]; gy [B][M] and gwfc [N][M] are
+ * nullable.  Returns L. */
+double orc_backward(const orc_net *net, const double *wfc, const double *const *w,
+                    const double *const *b, const double *y, const double *x, int B,
+                    double *const *gw, double *const *gb, double *gy, double *gwfc);
+
+/* One Adam step (Kingma & Ba) on n parameters; t is the 1-based step count. */
+void orc_adam(double *theta, const double *g, double *m, double *v, long n, long t,
+              double lr, double beta1, double beta2, double eps);
+
+/* PSNR = 10 log10(peak^2 / MSE) with peak = max_p x[p] (Sec. 5 footnote). */
+double orc_psnr(const double *xhat, const double *x, int N);
+/* ||a - ref||_2 / ||ref||_2 (absolute error when ||ref|| = 0). */
+double orc_relerr(const double *a, const double *ref, int N);
+/* Success indicator of Sec. 5: 1 if ||xhat - x||^2 / ||x||^2 <= thr. */
+int orc_success(const double *xhat, const double *x, int N, double thr);
+
+/* Orthonormal DCT-II matrix C[k][i] = a_k cos(pi (2i+1) k / 2n), a_0 = sqrt(1/n),
+ * a_k = sqrt(2/n).  2-D: coefficients S = C X C^T, image X = C^T S C. */
+void orc_dct_matrix(int n, double *C);
+
+/* Largest singular value of phi [M][N] by power iteration. */
+double orc_spectral_norm(const double *phi, int M, int N, int iters);
+
+/* ISTA (iterative soft thresholding) for min 1/2||y - A s||^2 + lam ||s||_1
+ * with A = Phi Psi, Psi the 2-D orthonormal inverse DCT on n1 x n2 images.
+ * Continuation: lam_0 = 0.5 ||A^T y||_inf, `stages` stages of `iters`
+ * iterations, lam <- decay * lam between stages; then a least-squares debias
+ * on the support {|s_j| > 1e-6 max|s|}.  s and x receive the coefficients
+ * [n1][n2] and the image [n1][n2].  Returns the support size. */
+int orc_ista_dct(const double *phi, const double *y, int M, int n1, int n2, int stages,
+                 int iters, double decay, double *s, double *x);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
