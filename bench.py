@@ -1,0 +1,193 @@
+"""Benchmark of the DeepInverse recovery path on one MI355X.
+
+Workload (the configuration the headline metric is quoted on): 64 x 64 images
+(N = 4096), M = 1024 measurements (M/N = 0.25), batch 256, the paper's
+1 -> 64 -> 32 -> 1 network with 11 x 11 filters; synthetic piecewise-smooth
+images, Gaussian Phi, He-initialised weights.  A step is one recovery
+(dsi_recover: proxy GEMM, three conv layers) of one batch whose measurements
+are already resident in HBM.
+
+Prints ONE JSON line: images/s of the BF16 path (value), the FP32 path beside
+it, per-batch latency percentiles, per-stage times, the roofline of the
+dominant kernel (conv layer 2) and the FP64 CPU oracle's rate on a sample of
+the same workload (which also gives the error and PSNR loss of the BF16 and
+FP32 outputs against FP64 on that sample).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "images recovered/s (64×64, M/N=0.25) bf16 vs fp32; p99 latency; ΔPSNR vs FP64"
+PEAK_BF16_TFLOPS = 2500.0   # MI355X dense BF16 MFMA
+PEAK_FP32_TFLOPS = 157.3
+N1 = N2 = 64
+M = 1024
+BATCH = 256
+
+
+def conv2_flops(B, N):
+    """Algorithmic flops of conv layer 2 (64 -> 32 channels, 11 x 11) per launch."""
+    return 2.0 * 64 * 32 * 121 * N * B
+
+
+def path_flops(B, N, M):
+    """2MN + 2 k^2 N (C0C1 + C1C2 + C2C3) per image (proxy + three conv layers)."""
+    return B * (2.0 * M * N + 2.0 * 121 * N * (64 + 64 * 32 + 32))
+
+
+def make_inputs(ctx, P, torch, cfg_id=2):
+    import synth
+    N = N1 * N2
+    phi = synth.make_phi(M, N, cfg_id=cfg_id)
+    x = synth.piecewise_smooth_images(BATCH, N1, N2, cfg_id=cfg_id).reshape(BATCH, N)
+    prm = synth.he_init(synth.PAPER_ARCH, N1, N2, bias_per_pixel=True, cfg_id=cfg_id)
+    dev = "cuda:0"
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+    phi_d, x_d = t(phi), t(x)
+    y = ctx.measure(phi_d, x_d)          # measurements resident in HBM
+    return phi, x, prm, params, x_d, y
+
+
+def time_path(ctx, net, y, steps, warmup, torch, stage_timing):
+    from paper_1701_03891_amd import _lib
+    B = y.shape[0]
+    xh = torch.empty((B, N1, N2), dtype=torch.float32, device=y.device)
+    for _ in range(warmup):
+        net.recover(y, xh)
+    torch.cuda.synchronize()
+    s = torch.cuda.current_stream()
+    ev = [torch.cuda.Event(enable_timing=True) for _ in range(steps + 1)]
+    if stage_timing:
+        _lib.dsi_stage_times(ctx.h)   # drop anything recorded before
+        _lib.dsi_set_stage_timing(ctx.h, 1)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    ev[0].record(s)
+    for k in range(steps):
+        net.recover(y, xh)
+        ev[k + 1].record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    if stage_timing:
+        _lib.dsi_set_stage_timing(ctx.h, 0)
+    per = np.array([ev[k].elapsed_time(ev[k + 1]) for k in range(steps)])
+    total_ms = ev[0].elapsed_time(ev[steps])
+    stages = None
+    if stage_timing:
+        ms, calls = _lib.dsi_stage_times(ctx.h, 4)
+        stages = {name: ms[q] / max(calls, 1) for q, name in
+                  enumerate(["proxy_gemm", "conv1", "conv2", "conv3"])}
+    return dict(total_ms=total_ms, wall_s=wall, per_step_ms=per, stages=stages, xhat=xh)
+
+
+def cpu_baseline(phi, x, prm, y_host, xh_bf16, xh_f32, n_img):
+    """The FP64 oracle on the first n_img images of the batch, on this host's cores."""
+    import oracle
+    threads = min(16, os.cpu_count() or 1)
+    oracle.set_threads(threads)
+    net = oracle.Net(N1, N2, M, bias_full=True)
+    bfull = [oracle.full_bias_from_cropped(prm.b[l], 11) for l in range(3)]
+    t0 = time.perf_counter()
+    ref = oracle.forward(net, phi.T, prm.w, bfull, y_host[:n_img])
+    dt = time.perf_counter() - t0
+    xs = x[:n_img]
+    ps64 = oracle.psnr(ref, xs)
+    out = {"value": n_img / dt, "unit": "images/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {n_img} of the 256 images (64x64, M=1024), FP64 C oracle, {dt:.1f} s"}
+    acc = {}
+    for name, xh in (("bf16", xh_bf16), ("f32", xh_f32)):
+        xh = xh[:n_img].reshape(n_img, -1).astype(np.float64)
+        rel = oracle.relerr(xh, ref)
+        dps = ps64 - oracle.psnr(xh, xs)
+        acc[name] = {"max_relerr_vs_fp64": float(rel.max()), "dpsnr_mean_db": float(dps.mean()),
+                     "dpsnr_max_abs_db": float(np.abs(dps).max())}
+    return out, acc
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=10)
+    ap.add_argument("--cpu-images", type=int, default=96, help="images in the oracle's timed sample")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+              "(images are independent, so N GPUs would each run this benchmark on their own batch)",
+              file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1701_03891_amd as P
+
+    ctx = P.Context(0)
+    phi, x, prm, params, x_d, y = make_inputs(ctx, P, torch)
+    N = N1 * N2
+    res = {}
+    for prec in ("bf16", "f32"):
+        net = ctx.prepare(N1, N2, M, params, prec=prec)
+        net.reserve(BATCH)
+        r = time_path(ctx, net, y, args.steps, args.warmup, torch, stage_timing=True)
+        r["xhat_host"] = r["xhat"].cpu().numpy()
+        res[prec] = r
+        net.free()
+
+    b = res["bf16"]
+    ms_step = b["total_ms"] / args.steps
+    value = BATCH * args.steps / (b["total_ms"] / 1e3)
+    f = res["f32"]
+    f_ms = f["total_ms"] / args.steps
+    c2_ms = b["stages"]["conv2"]
+    achieved = conv2_flops(BATCH, N) / (c2_ms / 1e3) / 1e12
+    out = {
+        "metric": METRIC,
+        "value": value,
+        "unit": "images/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "bf16",
+        "data": "synthetic",
+        "config": {"workload": "DeepInverse recovery, 64x64 images, M=1024 (M/N=0.25), batch 256, "
+                               "1->64->32->1 conv 11x11, He-init",
+                   "global_batch": BATCH, "image": [N1, N2], "M": M, "parallelism": "single GPU"},
+        "fp32": {"value": BATCH * args.steps / (f_ms * args.steps / 1e3), "ms_per_step": f_ms,
+                 "stages_ms": f["stages"]},
+        "speedup_bf16_vs_fp32": f_ms / ms_step,
+        "latency_ms_per_batch": {"p50": float(np.percentile(b["per_step_ms"], 50)),
+                                 "p99": float(np.percentile(b["per_step_ms"], 99)),
+                                 "fp32_p99": float(np.percentile(f["per_step_ms"], 99))},
+        "stages_ms": b["stages"],
+        "path_tflops": path_flops(BATCH, N, M) / (ms_step / 1e3) / 1e12,
+        "roofline": {"kernel": "conv_mid (conv layer 2, 64->32, 11x11)", "bound": "mfma",
+                     "achieved": achieved, "peak": PEAK_BF16_TFLOPS, "unit": "TFLOP/s",
+                     "frac": achieved / PEAK_BF16_TFLOPS, "traffic": None},
+        "cpu_baseline": None,
+    }
+    if not args.no_cpu:
+        y_host = y.cpu().numpy().astype(np.float64)
+        cb, acc = cpu_baseline(phi, x, prm, y_host, res["bf16"]["xhat_host"], res["f32"]["xhat_host"],
+                               args.cpu_images)
+        out["cpu_baseline"] = cb
+        out["accuracy_vs_fp64_on_sample"] = acc
+    ctx.close()
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

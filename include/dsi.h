@@ -1,0 +1,201 @@
+/*
+ * dsi.h -- C ABI of libdsi, a single-GPU (MI355X, gfx950) implementation of the
+ * DeepInverse recovery path (Mousavi & Baraniuk, "Learning to Invert: Signal
+ * Recovery via Deep Convolutional Networks", arXiv 1701.03891).
+ *
+ * The path, as the paper defines it:
+ *   - measurement  y = Phi x, Phi an M x N matrix, M << N            (Sec. 1)
+ *   - proxy        x~ = Phi^T y, a fixed fully connected layer,
+ *                  read as an n1 x n2 image (n1 n2 = N)                 (Sec. 4)
+ *   - L conv layers, each S(ReLU(W * a + b)) with zero padding and a
+ *                  crop S back to n1 x n2; 1 -> 64 -> 32 -> 1 channels,
+ *                  11 x 11 filters in the paper's experiments          (Sec. 4 Eq. 1, Sec. 5)
+ *   - training     L(Omega) = (1/l) sum_i ||M(y_i, Omega) - x_i||^2,
+ *                  minimised by backpropagation                        (Sec. 4)
+ *
+ * Conventions shared by every call:
+ *   - Tensor pointers are DEVICE pointers, allocated and owned by the caller,
+ *     unless a comment says "host".  The library never frees or reallocates
+ *     caller memory.  Device buffers must be 16-byte aligned.
+ *   - Images are row-major: pixel p = i*n2 + j.  Batches are outermost.
+ *   - "*" in Eq. (1) is taken as 2-D cross-correlation; the crop S of the full
+ *     correlation is the centred "same" output with zero padding (k-1)/2.
+ *   - Work is enqueued on the caller's HIP stream (`stream`, a hipStream_t;
+ *     NULL is the default stream).  No call synchronises the device except
+ *     where stated; errors from kernels that already ran surface as DSI_E_HIP
+ *     on a later call.
+ *   - Every call returns a dsi_status.  Argument errors are detected before
+ *     any launch and leave every output untouched; dsi_last_error() gives a
+ *     thread-local message for the last failure on the calling thread.
+ *   - One dsi_ctx per host thread, or external locking.  Calls on one ctx that
+ *     share its workspace must be ordered on one stream.
+ */
+#ifndef DSI_H
+#define DSI_H
+
+#include <stddef.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  DSI_OK = 0,
+  DSI_E_NULL = 1,   /* a required pointer is NULL */
+  DSI_E_SHAPE = 2,  /* a size is out of range or inconsistent */
+  DSI_E_DTYPE = 3,  /* unsupported precision for this network */
+  DSI_E_ALIGN = 4,  /* a device pointer is not 16-byte aligned */
+  DSI_E_NOMEM = 5,  /* device allocation failed */
+  DSI_E_HIP = 6,    /* a HIP runtime call or an earlier kernel failed */
+  DSI_E_STATE = 7   /* object used in a state that does not allow the call */
+} dsi_status;
+
+typedef enum {
+  DSI_F32 = 0,      /* FP32 operands, FP32 accumulation */
+  DSI_BF16 = 1,     /* BF16 operands (round to nearest even), FP32 accumulation */
+  DSI_FP8_E4M3 = 2, /* OCP FP8 e4m3 operands with power-of-two per-tensor scales, FP32 accumulation */
+  DSI_F64 = 3       /* FP64 throughout (checking only: finite-difference gradient checks) */
+} dsi_prec;
+
+typedef struct dsi_ctx dsi_ctx; /* device, workspace */
+typedef struct dsi_net dsi_net; /* prepared network: packed and cast weights */
+
+#define DSI_MAX_LAYERS 8
+
+/* Architecture of the network (Sec. 4, Sec. 5).  The paper's network is
+ * L = 3, C = {1, 64, 32, 1}, k = {11, 11, 11}. */
+typedef struct {
+  int n1, n2;          /* image rows and columns; N = n1*n2 */
+  int M;               /* number of measurements (M >= 1; M < N is typical, not required) */
+  int L;               /* number of conv layers, 1..DSI_MAX_LAYERS */
+  int C[DSI_MAX_LAYERS + 1]; /* channel counts; C[0] = C[L] = 1 */
+  int k[DSI_MAX_LAYERS];     /* odd filter sizes */
+  int bias_per_pixel;  /* 1: per-pixel bias [Cout][n1][n2] -- Eq. (1)'s full-grid bias after
+                          the crop S, whose border entries never reach the output;
+                          0: one bias per output channel [Cout] */
+  int relu_last;       /* 1: ReLU after the last layer as well (Sec. 4 applies ReLU in every
+                          layer); 0: linear last layer, so signed signals stay representable */
+} dsi_net_desc;
+
+/* Parameters Omega (Sec. 4), FP32.  Device pointers.  For dsi_net_prepare and
+ * dsi_net_update they are read only; for dsi_train_step they are the FP32 master
+ * copy, updated in place. */
+typedef struct {
+  float *w_fc;                  /* [N][M] row-major; Phi^T for the paper's fixed layer */
+  float *w[DSI_MAX_LAYERS];     /* [Cout][Cin][k][k] */
+  float *b[DSI_MAX_LAYERS];     /* [Cout][n1][n2] if bias_per_pixel, else [Cout] */
+} dsi_params;
+
+/* Gradients, same shapes as dsi_params, FP32 device pointers (w_fc unused). */
+typedef dsi_params dsi_grads;
+
+/* Adam state (Kingma & Ba): first and second moments with the shapes of
+ * w[l] and b[l], FP32 device pointers, zero before the first step. */
+typedef struct {
+  float *m_w[DSI_MAX_LAYERS], *v_w[DSI_MAX_LAYERS];
+  float *m_b[DSI_MAX_LAYERS], *v_b[DSI_MAX_LAYERS];
+  float beta1, beta2, eps;      /* 0.9, 0.999, 1e-8 */
+  long step;                    /* completed steps; dsi_train_step increments it (host field) */
+} dsi_adam;
+
+/* ------------------------------------------------------------ lifetime */
+/* Create a context on HIP device `device`.  *out receives the handle. */
+dsi_status dsi_create(dsi_ctx **out, int device);
+/* Destroy a context and its workspace.  Waits for the device to go idle. */
+dsi_status dsi_destroy(dsi_ctx *ctx);
+/* Thread-local message of the last error on this thread ("" if none). */
+const char *dsi_last_error(void);
+/* Library version string. */
+const char *dsi_version(void);
+
+/* ---------------------------------------------------- Sec. 1: y = Phi x */
+/* y[b][m] = sum_n phi[m][n] x[b][n], FP32 in and out, FP32 accumulation.
+ * phi [M][N], x [B][N], y [B][M].  B = 0 is an empty batch (no-op). */
+dsi_status dsi_measure(dsi_ctx *ctx, const float *phi, const float *x, float *y,
+                       int B, int M, int N, void *stream);
+
+/* ------------------------------------------- Sec. 4: the recovery network */
+/* Validate `desc`, copy and pack `params` into the precision `prec`, and
+ * return a prepared network in *out.  The packed copies are owned by the
+ * network; `params` may be freed afterwards.  Runs on `stream` and waits for
+ * it before returning.  Precisions: DSI_F32 and DSI_F64 for every
+ * architecture; DSI_BF16 and DSI_FP8_E4M3 for the paper's architecture
+ * (C = {1,64,32,1}, k = 11), else DSI_E_DTYPE. */
+dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_params *params,
+                           dsi_prec prec, dsi_net **out, void *stream);
+/* Re-pack the network's copies from new parameter values (same shapes). Enqueued on stream. */
+dsi_status dsi_net_update(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, void *stream);
+/* FP8 only: static per-tensor activation scales (host array of L+1 floats:
+ * the proxy and the input of every further layer), each a positive power of
+ * two; dequantised value = code * scale.  Without this call every scale is 1. */
+dsi_status dsi_net_set_act_scales(dsi_net *net, const float *scales_host, int n);
+/* Free a prepared network (device memory is released after the device idles). */
+dsi_status dsi_net_free(dsi_ctx *ctx, dsi_net *net);
+/* Query the net's precision and description (host outputs, nullable). */
+dsi_status dsi_net_info(const dsi_net *net, dsi_net_desc *desc, dsi_prec *prec);
+
+/* Bytes of training state one batch of B images needs (`saved` of
+ * dsi_forward_train).  train = 0 gives the recovery workspace instead. */
+dsi_status dsi_workspace_size(const dsi_net *net, int B, int train, size_t *bytes);
+/* Grow the context's workspace now to serve batches of up to B images of this
+ * net (so later calls do not allocate, e.g. under stream capture). Synchronous. */
+dsi_status dsi_reserve(dsi_ctx *ctx, const dsi_net *net, int B, int train);
+
+/* xhat = M(y, Omega) (Sec. 4): proxy x~ = W_fc y, then every conv layer of
+ * Eq. (1).  y [B][M] FP32, xhat [B][n1][n2] FP32.  B = 0 is a no-op. */
+dsi_status dsi_recover(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
+                       void *stream);
+
+/* ------------------------------------------------- Sec. 4: backpropagation */
+/* Forward pass that also keeps, in `saved` (caller-owned device buffer of at
+ * least dsi_workspace_size(net, B, 1) bytes), what the backward pass needs. */
+dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat,
+                             int B, void *saved, size_t saved_bytes, void *stream);
+/* Backward pass of a loss with gradient gxhat = dL/dxhat [B][n1][n2] (FP32),
+ * from the state dsi_forward_train left in `saved` for the same y and B.
+ * Writes dL/dw[l] and dL/db[l] into grads (overwriting) and, if gy is not
+ * NULL, dL/dy [B][M].  Parameter gradients are summed over the batch in a
+ * fixed order, so repeated calls give identical bits. */
+dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, const void *saved,
+                        size_t saved_bytes, int B, const dsi_grads *grads, float *gy,
+                        void *stream);
+/* Loss L = (1/B) sum_b ||xhat_b - x_b||^2 (Sec. 4, accumulated in FP64) and
+ * its gradient with respect to every parameter (into grads, overwriting) and,
+ * if gy is not NULL, to y [B][M]: forward, dL/dxhat = (2/B)(xhat - x), backward.
+ * loss_dev (nullable) is a device double that receives L. */
+dsi_status dsi_loss_grad(dsi_ctx *ctx, dsi_net *net, const float *y, const float *x, int B,
+                         const dsi_grads *grads, float *gy, double *loss_dev, void *stream);
+/* One training step on a batch (Sec. 4): forward in the net's precision, loss
+ * L = (1/B) sum_b ||xhat_b - x_b||^2 (accumulated in FP64), backward, Adam
+ * update (lr) of the FP32 master parameters `params` (w and b; w_fc stays
+ * fixed, as in the paper), and a re-pack of the net from them.  y [B][M],
+ * x [B][n1][n2].  loss_dev (nullable) is a device double that receives L.
+ * opt->step is incremented on the host. */
+dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, dsi_adam *opt,
+                          const float *y, const float *x, int B, float lr, double *loss_dev,
+                          void *stream);
+
+/* ---------------------------------------------------- Sec. 5: metrics */
+/* Per image b, in FP64 on the device, out[b][4] =
+ *   { ||xhat_b - x_b||^2,
+ *     PSNR = 10 log10(max_p x_b[p]^2 / MSE_b)   (Sec. 5 footnote),
+ *     ||xhat_b - x_b|| / ||x_b||,
+ *     success phi = 1 if ||xhat_b - x_b||^2 / ||x_b||^2 <= 0.1 else 0  (Sec. 5) }.
+ * xhat, x [B][N] FP32; out [B][4] device doubles. */
+dsi_status dsi_metrics(dsi_ctx *ctx, const float *xhat, const float *x, int B, int N,
+                       double *out, void *stream);
+
+/* ---------------------------------------------------- benchmarking */
+/* When enabled, every forward pass through the paper's network records HIP
+ * events on the caller's stream at the boundaries of its stages {proxy GEMM,
+ * conv layer 1, conv layer 2, conv layer 3}. */
+dsi_status dsi_set_stage_timing(dsi_ctx *ctx, int enable);
+/* Waits for the recorded events, writes the milliseconds spent in each of the
+ * first `nstages` stages summed over the timed passes into ms (host array) and
+ * their number into *calls (host), then forgets them. */
+dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSI_H */

@@ -1,0 +1,793 @@
+// api.cpp -- the C ABI of libdsi (declared in include/dsi.h): argument
+// validation, weight packing, workspace layout and the launch sequence of the
+// DeepInverse recovery path on one GPU.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdint>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "../../include/dsi.h"
+#include "internal.h"
+
+using dsi::ActView;
+using bf16 = __bf16;
+
+namespace {
+
+thread_local std::string g_err;
+
+dsi_status fail(dsi_status st, const char *fmt, ...) {
+  char buf[512];
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(buf, sizeof buf, fmt, ap);
+  va_end(ap);
+  g_err = buf;
+  return st;
+}
+
+#define HIPCHK(expr)                                                                         \
+  do {                                                                                       \
+    hipError_t e_ = (expr);                                                                  \
+    if (e_ != hipSuccess) return fail(DSI_E_HIP, "%s: %s", #expr, hipGetErrorString(e_));    \
+  } while (0)
+
+bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+size_t rnd(size_t x) { return (x + 255) & ~size_t(255); }
+
+enum Path { PATH_GENERIC = 0, PATH_PAPER = 1 };
+
+bool is_paper_arch(const dsi_net_desc &d) {
+  return d.L == 3 && d.C[0] == 1 && d.C[1] == 64 && d.C[2] == 32 && d.C[3] == 1 && d.k[0] == 11 &&
+         d.k[1] == 11 && d.k[2] == 11;
+}
+
+size_t elem_size(dsi_prec p) {
+  switch (p) {
+    case DSI_BF16: return 2;
+    case DSI_FP8_E4M3: return 1;
+    case DSI_F64: return 8;
+    default: return 4;
+  }
+}
+
+}  // namespace
+
+struct dsi_ctx {
+  int device = 0;
+  void *ws = nullptr;
+  size_t ws_bytes = 0;
+  // stage timing (benchmarking): one set of events per timed forward pass
+  int timing = 0;
+  std::vector<std::vector<hipEvent_t>> ev;
+};
+
+namespace {
+// Records the boundary event of stage `k` of the current forward pass.
+struct StageClock {
+  dsi_ctx *ctx;
+  hipStream_t s;
+  std::vector<hipEvent_t> *set = nullptr;
+  StageClock(dsi_ctx *c, hipStream_t st) : ctx(c), s(st) {
+    if (ctx && ctx->timing) {
+      ctx->ev.emplace_back();
+      set = &ctx->ev.back();
+    }
+  }
+  void mark() {
+    if (!set) return;
+    hipEvent_t e;
+    if (hipEventCreate(&e) == hipSuccess) {
+      (void)hipEventRecord(e, s);
+      set->push_back(e);
+    }
+  }
+};
+}  // namespace
+
+struct dsi_net {
+  dsi_net_desc d{};
+  dsi_prec prec = DSI_F32;
+  int path = PATH_GENERIC;
+  int N = 0, Mpad = 0;
+  size_t es = 4;          // bytes per compute element
+  void *wfc = nullptr;    // [N][Mpad] compute precision
+  float *wfcT = nullptr;  // [M][N] fp32, built on first use (input gradient)
+  // generic path: OIHW weights and biases in compute precision (float or double)
+  void *w[DSI_MAX_LAYERS] = {};
+  void *b[DSI_MAX_LAYERS] = {};
+  // paper path
+  void *wp1 = nullptr, *wp2 = nullptr, *wp3 = nullptr;  // packed (compute precision)
+  float *bp[3] = {};                                     // fp32 biases, per-pixel ones as [H][W][C]
+  float *w32[3] = {};                                    // OIHW fp32 copies (backward)
+  float *b32[3] = {};                                    // fp32 biases in caller layout (backward)
+  float act_scale[DSI_MAX_LAYERS + 1];
+};
+
+namespace {
+
+// ------------------------------------------------------------ validation
+dsi_status check_desc(const dsi_net_desc *d) {
+  if (!d) return fail(DSI_E_NULL, "desc is NULL");
+  if (d->n1 < 1 || d->n2 < 1 || (long)d->n1 * d->n2 > (1L << 28))
+    return fail(DSI_E_SHAPE, "image size %d x %d out of range", d->n1, d->n2);
+  if (d->M < 1) return fail(DSI_E_SHAPE, "M = %d must be >= 1", d->M);
+  if (d->L < 1 || d->L > DSI_MAX_LAYERS) return fail(DSI_E_SHAPE, "L = %d out of range", d->L);
+  if (d->C[0] != 1 || d->C[d->L] != 1) return fail(DSI_E_SHAPE, "C[0] and C[L] must be 1");
+  for (int l = 0; l < d->L; ++l) {
+    if (d->C[l + 1] < 1 || d->C[l + 1] > 4096) return fail(DSI_E_SHAPE, "C[%d] = %d out of range", l + 1, d->C[l + 1]);
+    if (d->k[l] < 1 || (d->k[l] & 1) == 0 || d->k[l] > 63) return fail(DSI_E_SHAPE, "k[%d] = %d must be odd, 1..63", l, d->k[l]);
+  }
+  return DSI_OK;
+}
+
+dsi_status check_params(const dsi_net_desc &d, const dsi_params *p) {
+  if (!p) return fail(DSI_E_NULL, "params is NULL");
+  if (!p->w_fc) return fail(DSI_E_NULL, "params->w_fc is NULL");
+  if (!aligned16(p->w_fc)) return fail(DSI_E_ALIGN, "params->w_fc not 16-byte aligned");
+  for (int l = 0; l < d.L; ++l) {
+    if (!p->w[l] || !p->b[l]) return fail(DSI_E_NULL, "params w/b of layer %d is NULL", l);
+    if (!aligned16(p->w[l]) || !aligned16(p->b[l])) return fail(DSI_E_ALIGN, "params of layer %d not 16-byte aligned", l);
+  }
+  return DSI_OK;
+}
+
+long wcount(const dsi_net_desc &d, int l) { return (long)d.C[l + 1] * d.C[l] * d.k[l] * d.k[l]; }
+long bcount(const dsi_net_desc &d, int l) { return d.bias_per_pixel ? (long)d.C[l + 1] * d.n1 * d.n2 : d.C[l + 1]; }
+
+// --------------------------------------------------------- workspace layout
+struct Layout {
+  size_t ypad = 0, xt = 0, act[DSI_MAX_LAYERS + 1] = {}, xh64 = 0, y64 = 0, end = 0;
+};
+
+// Recovery workspace (train = 0) or training state (train = 1) for B images.
+// Paper path: ypad fp32 [B][Mpad], xt [B][N] T, a1 [B][64][N] T, a2 [B][32][N] T
+//   (+ z3 fp32 [B][N] when training).
+// Generic path: xt and a_l [B][C_l][N] in compute precision (+ y64 for FP64).
+Layout layout(const dsi_net &n, int B, int train) {
+  Layout L;
+  size_t off = 0;
+  const size_t N = (size_t)n.N, es = n.es;
+  L.ypad = off; off += rnd((size_t)B * n.Mpad * (n.prec == DSI_F64 ? 8 : 4));
+  L.xt = off; off += rnd((size_t)B * N * es);
+  for (int l = 1; l <= n.d.L; ++l) {
+    L.act[l] = off;
+    const bool last = l == n.d.L;
+    if (last && !train && !(n.prec == DSI_F64)) { L.act[l] = SIZE_MAX; continue; }  // written to xhat directly
+    off += rnd((size_t)B * n.d.C[l] * N * (last && n.path == PATH_PAPER ? 4 : es));
+  }
+  L.end = off;
+  return L;
+}
+
+template <typename T> T *at(void *base, size_t off) { return reinterpret_cast<T *>((char *)base + off); }
+
+dsi_status ensure_ws(dsi_ctx *ctx, size_t bytes) {
+  if (bytes <= ctx->ws_bytes) return DSI_OK;
+  if (ctx->ws) {
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipFree(ctx->ws));
+    ctx->ws = nullptr;
+    ctx->ws_bytes = 0;
+  }
+  if (hipMalloc(&ctx->ws, bytes) != hipSuccess) {
+    ctx->ws = nullptr;
+    return fail(DSI_E_NOMEM, "workspace allocation of %zu bytes failed", bytes);
+  }
+  ctx->ws_bytes = bytes;
+  return DSI_OK;
+}
+
+dsi_status set_device(dsi_ctx *ctx) {
+  HIPCHK(hipSetDevice(ctx->device));
+  return DSI_OK;
+}
+
+void free_net_buffers(dsi_net *n) {
+  auto f = [](void *&p) { if (p) { (void)hipFree(p); p = nullptr; } };
+  f(n->wfc);
+  void *t = n->wfcT; f(t); n->wfcT = nullptr;
+  for (int l = 0; l < DSI_MAX_LAYERS; ++l) { f(n->w[l]); f(n->b[l]); }
+  f(n->wp1); f(n->wp2); f(n->wp3);
+  for (int l = 0; l < 3; ++l) {
+    void *a = n->bp[l]; f(a); n->bp[l] = nullptr;
+    void *c = n->w32[l]; f(c); n->w32[l] = nullptr;
+    void *e = n->b32[l]; f(e); n->b32[l] = nullptr;
+  }
+}
+
+dsi_status alloc(void **p, size_t bytes) {
+  if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
+    *p = nullptr;
+    return fail(DSI_E_NOMEM, "allocation of %zu bytes failed", bytes);
+  }
+  return DSI_OK;
+}
+
+// copy/convert parameters into the net's own storage (enqueued on s)
+dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
+  const dsi_net_desc &d = n->d;
+  const int N = n->N, HW = N;
+  const int pr = n->prec == DSI_BF16 ? 1 : 0;
+  if (n->prec == DSI_F64) {
+    // FP64: W_fc [N][M] as double (unpadded), OIHW weights and biases as double
+    HIPCHK(dsi::cast_f32_f64(p->w_fc, (double *)n->wfc, (long)N * d.M, s));
+    for (int l = 0; l < d.L; ++l) {
+      HIPCHK(dsi::cast_f32_f64(p->w[l], (double *)n->w[l], wcount(d, l), s));
+      HIPCHK(dsi::cast_f32_f64(p->b[l], (double *)n->b[l], bcount(d, l), s));
+    }
+    return DSI_OK;
+  }
+  HIPCHK(dsi::pack_fc(p->w_fc, n->wfc, N, d.M, n->Mpad, pr, s));
+  if (n->wfcT) {
+    (void)hipFree(n->wfcT);
+    n->wfcT = nullptr;
+  }
+  if (n->path == PATH_GENERIC) {
+    for (int l = 0; l < d.L; ++l) {
+      HIPCHK(hipMemcpyAsync(n->w[l], p->w[l], wcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+      HIPCHK(hipMemcpyAsync(n->b[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    }
+    return DSI_OK;
+  }
+  HIPCHK(dsi::pack_first(p->w[0], n->wp1, pr, s));
+  HIPCHK(dsi::pack_mid(p->w[1], n->wp2, 64, 32, 0, pr, s));
+  HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, pr, s));
+  for (int l = 0; l < 3; ++l) {
+    const int C = d.C[l + 1];
+    if (d.bias_per_pixel && C > 1) HIPCHK(dsi::pack_bias_hwc(p->b[l], n->bp[l], C, HW, s));
+    else HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(n->w32[l], p->w[l], wcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(n->b32[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+  }
+  return DSI_OK;
+}
+
+// ---------------------------------------------------------------- forward
+// Runs the proxy and every conv layer; keeps activations in ws at L (train or not).
+dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *xhat, int B, void *base,
+                        const Layout &L, hipStream_t s) {
+  const dsi_net_desc &d = n->d;
+  const int N = n->N, H = d.n1, W = d.n2, M = d.M;
+  (void)ctx;
+  if (n->prec == DSI_F64) {
+    double *y64 = at<double>(base, L.ypad);
+    double *xt = at<double>(base, L.xt);
+    HIPCHK(dsi::cast_f32_f64(y, y64, (long)B * M, s));
+    HIPCHK(dsi::gemm_nt_f64(y64, M, (const double *)n->wfc, M, xt, N, B, N, M, s));
+    const double *a = xt;
+    for (int l = 0; l < d.L; ++l) {
+      double *o = at<double>(base, L.act[l + 1]);
+      const int relu = (l < d.L - 1) || d.relu_last;
+      HIPCHK((dsi::conv_fwd_direct<double, double, double, double>(
+          a, ActView{d.C[l], H, W, 0}, (const double *)n->w[l], (const double *)n->b[l], d.bias_per_pixel,
+          relu, o, ActView{d.C[l + 1], H, W, 0}, B, d.k[l], s)));
+      a = o;
+    }
+    if (xhat) HIPCHK(dsi::cast_f64_f32(a, xhat, (long)B * N, s));
+    return DSI_OK;
+  }
+  // proxy x~ = W_fc y (K padded to Mpad with zeros)
+  const bool direct_y = (M % 16 == 0) && aligned16(y);
+  const float *yk = y;
+  long ldy = M;
+  if (!direct_y) {
+    float *yp = at<float>(base, L.ypad);
+    HIPCHK(dsi::pad_rows(y, yp, B, M, n->Mpad, 0, s));
+    yk = yp;
+    ldy = n->Mpad;
+  }
+  float *xout_last = (L.act[d.L] == SIZE_MAX) ? xhat : at<float>(base, L.act[d.L]);
+  StageClock clk(ctx, s);
+  clk.mark();
+  if (n->path == PATH_GENERIC) {
+    float *xt = at<float>(base, L.xt);
+    HIPCHK(dsi::gemm_nt_f32(yk, ldy, (const float *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
+    const float *a = xt;
+    for (int l = 0; l < d.L; ++l) {
+      float *o = (l == d.L - 1) ? xout_last : at<float>(base, L.act[l + 1]);
+      const int relu = (l < d.L - 1) || d.relu_last;
+      HIPCHK((dsi::conv_fwd_direct<float, float, float, float>(
+          a, ActView{d.C[l], H, W, 0}, (const float *)n->w[l], (const float *)n->b[l], d.bias_per_pixel, relu,
+          o, ActView{d.C[l + 1], H, W, 0}, B, d.k[l], s)));
+      a = o;
+    }
+  } else if (n->prec == DSI_BF16) {
+    bf16 *xt = at<bf16>(base, L.xt), *a1 = at<bf16>(base, L.act[1]), *a2 = at<bf16>(base, L.act[2]);
+    HIPCHK(dsi::gemm_nt_bf16_out_bf16(yk, ldy, (const bf16 *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
+    clk.mark();
+    HIPCHK(dsi::conv_first<bf16>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, a1, B, H, W, s));
+    clk.mark();
+    HIPCHK((dsi::conv_mid<bf16, 64, 32, dsi::EPI_BIAS, bf16>(a1, (const bf16 *)n->wp2, n->bp[1],
+                                                            d.bias_per_pixel, 1, nullptr, a2, B, H, W, s)));
+    clk.mark();
+    HIPCHK(dsi::conv_last<bf16>(a2, (const bf16 *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
+                                xout_last, B, H, W, s));
+    clk.mark();
+  } else {
+    float *xt = at<float>(base, L.xt), *a1 = at<float>(base, L.act[1]), *a2 = at<float>(base, L.act[2]);
+    HIPCHK(dsi::gemm_nt_f32(yk, ldy, (const float *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
+    clk.mark();
+    HIPCHK(dsi::conv_first<float>(xt, (const float *)n->wp1, n->bp[0], d.bias_per_pixel, a1, B, H, W, s));
+    clk.mark();
+    HIPCHK((dsi::conv_mid<float, 64, 32, dsi::EPI_BIAS, float>(a1, (const float *)n->wp2, n->bp[1],
+                                                              d.bias_per_pixel, 1, nullptr, a2, B, H, W, s)));
+    clk.mark();
+    HIPCHK(dsi::conv_last<float>(a2, (const float *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
+                                 xout_last, B, H, W, s));
+    clk.mark();
+  }
+  if (xhat && xout_last != xhat)
+    HIPCHK(hipMemcpyAsync(xhat, xout_last, (size_t)B * N * 4, hipMemcpyDeviceToDevice, s));
+  return DSI_OK;
+}
+
+// --------------------------------------------------------------- backward
+// gz_last: dL/dz of the last layer (already masked when relu_last), [B][N] in the
+// path's gradient precision (fp32, or fp64 for DSI_F64).  Scratch for the
+// gradients of the hidden layers comes after the saved state in ws2.
+dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, const void *saved,
+                         const Layout &L, int B, const dsi_grads *g, float *gy, void *scratch,
+                         hipStream_t s) {
+  const dsi_net_desc &d = n->d;
+  const int N = n->N, H = d.n1, W = d.n2, M = d.M;
+  (void)ctx;
+  void *sv = const_cast<void *>(saved);
+  if (n->prec == DSI_F64) {
+    // two ping-pong gradient buffers of the widest layer, in double
+    int cmax = 1;
+    for (int l = 0; l <= d.L; ++l) cmax = std::max(cmax, d.C[l]);
+    double *gbuf[2] = {at<double>(scratch, 0), at<double>(scratch, rnd((size_t)B * cmax * N * 8))};
+    double *wtmp = at<double>(scratch, 2 * rnd((size_t)B * cmax * N * 8));
+    const double *gz = (const double *)gz_last;
+    for (int l = d.L - 1; l >= 0; --l) {
+      const double *in = l == 0 ? at<double>(sv, L.xt) : at<double>(sv, L.act[l]);
+      ActView vg{d.C[l + 1], H, W, 0}, vi{d.C[l], H, W, 0};
+      HIPCHK((dsi::conv_wgrad_direct<double, double, double, double>(gz, vg, in, vi, B, d.k[l], wtmp, s)));
+      HIPCHK(dsi::cast_f64_f32(wtmp, g->w[l], wcount(d, l), s));
+      HIPCHK((dsi::bias_grad<double, double, double>(gz, vg, B, d.bias_per_pixel, wtmp, s)));
+      HIPCHK(dsi::cast_f64_f32(wtmp, g->b[l], bcount(d, l), s));
+      if (l == 0 && !gy) break;
+      double *go = gbuf[l & 1];
+      HIPCHK((dsi::conv_dgrad_direct<double, double, double, double, double>(
+          gz, vg, (const double *)n->w[l], l > 0 ? in : nullptr, vi, go, vi, B, d.k[l], s)));
+      gz = go;
+    }
+    if (gy) {
+      // dy[b][m] = sum_p W_fc[p][m] g_xt[b][p]: transpose W_fc into wtmp as [M][N]
+      double *wT = wtmp;
+      double *g64 = at<double>(scratch, 2 * rnd((size_t)B * cmax * N * 8) + rnd((size_t)M * N * 8));
+      // no transposition kernel in double: use the generic GEMM with X = g_xt, W = W_fc^T
+      // built by a strided copy on the host side of the stream (small: checking path only)
+      HIPCHK(hipMemcpy2DAsync(wT, 8, n->wfc, (size_t)M * 8, 8, N, hipMemcpyDeviceToDevice, s));
+      for (int m = 1; m < M; ++m)
+        HIPCHK(hipMemcpy2DAsync(wT + (size_t)m * N, 8, (const double *)n->wfc + m, (size_t)M * 8, 8, N,
+                                hipMemcpyDeviceToDevice, s));
+      HIPCHK(dsi::gemm_nt_f64(gz, N, wT, N, g64, M, B, M, N, s));
+      HIPCHK(dsi::cast_f64_f32(g64, gy, (long)B * M, s));
+    }
+    return DSI_OK;
+  }
+  // fp32 gradients; activations read in the path's storage (planar fp32, or blocked bf16/fp32)
+  const bool paper = n->path == PATH_PAPER;
+  int cmax = 1;
+  for (int l = 0; l <= d.L; ++l) cmax = std::max(cmax, d.C[l]);
+  float *gbuf[2] = {at<float>(scratch, 0), at<float>(scratch, rnd((size_t)B * cmax * N * 4))};
+  const float *gz = (const float *)gz_last;
+  for (int l = d.L - 1; l >= 0; --l) {
+    const bool in_blocked = paper && d.C[l] % 16 == 0;
+    ActView vg{d.C[l + 1], H, W, 0}, vi{d.C[l], H, W, in_blocked ? 1 : 0};
+    const void *in = l == 0 ? at<char>(sv, L.xt) : at<char>(sv, L.act[l]);
+    const float *wl = paper ? n->w32[l] : (const float *)n->w[l];
+    if (paper && n->prec == DSI_BF16) {
+      HIPCHK((dsi::conv_wgrad_direct<float, bf16, float, float>(gz, vg, (const bf16 *)in, vi, B, d.k[l], g->w[l], s)));
+    } else {
+      HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>(gz, vg, (const float *)in, vi, B, d.k[l], g->w[l], s)));
+    }
+    HIPCHK((dsi::bias_grad<float, float, float>(gz, vg, B, d.bias_per_pixel, g->b[l], s)));
+    if (l == 0 && !gy) break;
+    float *go = gbuf[l & 1];
+    ActView vo{d.C[l], H, W, 0};
+    if (paper && n->prec == DSI_BF16 && l > 0) {
+      HIPCHK((dsi::conv_dgrad_direct<float, float, bf16, float, float>(gz, vg, wl, (const bf16 *)in, vi, go, vo, B, d.k[l], s)));
+    } else {
+      HIPCHK((dsi::conv_dgrad_direct<float, float, float, float, float>(
+          gz, vg, wl, (l > 0 && !(paper && n->prec == DSI_BF16)) ? (const float *)in : nullptr, vi, go, vo, B,
+          d.k[l], s)));
+    }
+    gz = go;
+  }
+  if (gy) {
+    // dy = g_xt W_fc: X = g_xt [B][N], W = W_fc^T [M][N] (fp32, built once)
+    if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
+    HIPCHK(dsi::gemm_nt_f32(gz, N, n->wfcT, N, gy, M, B, M, N, N % 16 == 0, s));
+  }
+  return DSI_OK;
+}
+
+size_t backward_scratch_bytes(const dsi_net &n, int B) {
+  int cmax = 1;
+  for (int l = 0; l <= n.d.L; ++l) cmax = std::max(cmax, n.d.C[l]);
+  const size_t es = n.prec == DSI_F64 ? 8 : 4;
+  size_t b = 2 * rnd((size_t)B * cmax * n.N * es);
+  if (n.prec == DSI_F64) {
+    size_t wmax = 0;
+    for (int l = 0; l < n.d.L; ++l) wmax = std::max<size_t>(wmax, std::max(wcount(n.d, l), bcount(n.d, l)));
+    wmax = std::max<size_t>(wmax, (size_t)n.d.M * n.N);
+    b += rnd(wmax * 8) + rnd((size_t)B * n.d.M * 8);
+  }
+  b += rnd((size_t)B * n.N * es);   // gz of the last layer
+  b += rnd((size_t)B * 4 * 8) + 256; // per-image stats + loss
+  return b;
+}
+
+}  // namespace
+
+// ====================================================================== ABI
+extern "C" {
+
+const char *dsi_last_error(void) { return g_err.c_str(); }
+const char *dsi_version(void) { return "dsi 0.1 (gfx950)"; }
+
+dsi_status dsi_create(dsi_ctx **out, int device) {
+  if (!out) return fail(DSI_E_NULL, "out is NULL");
+  int count = 0;
+  if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(DSI_E_HIP, "no HIP device");
+  if (device < 0 || device >= count) return fail(DSI_E_SHAPE, "device %d out of range (%d devices)", device, count);
+  dsi_ctx *c = new (std::nothrow) dsi_ctx;
+  if (!c) return fail(DSI_E_NOMEM, "host allocation failed");
+  c->device = device;
+  *out = c;
+  return DSI_OK;
+}
+
+dsi_status dsi_destroy(dsi_ctx *ctx) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  if (ctx->ws) {
+    (void)hipSetDevice(ctx->device);
+    (void)hipDeviceSynchronize();
+    (void)hipFree(ctx->ws);
+  }
+  delete ctx;
+  return DSI_OK;
+}
+
+dsi_status dsi_measure(dsi_ctx *ctx, const float *phi, const float *x, float *y, int B, int M, int N,
+                       void *stream) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  if (B < 0 || M < 1 || N < 1) return fail(DSI_E_SHAPE, "bad sizes B=%d M=%d N=%d", B, M, N);
+  if (B == 0) return DSI_OK;
+  if (!phi || !x || !y) return fail(DSI_E_NULL, "phi, x and y must be non-NULL");
+  if (!aligned16(phi) || !aligned16(x) || !aligned16(y)) return fail(DSI_E_ALIGN, "phi, x, y must be 16-byte aligned");
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  const bool vec = N % 16 == 0;
+  HIPCHK(dsi::gemm_nt_f32(x, N, phi, N, y, M, B, M, N, vec, (hipStream_t)stream));
+  return DSI_OK;
+}
+
+dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_params *params,
+                           dsi_prec prec, dsi_net **out, void *stream) {
+  if (!ctx || !out) return fail(DSI_E_NULL, "ctx and out must be non-NULL");
+  dsi_status st = check_desc(desc);
+  if (st != DSI_OK) return st;
+  st = check_params(*desc, params);
+  if (st != DSI_OK) return st;
+  const bool paper = is_paper_arch(*desc);
+  if (prec != DSI_F32 && prec != DSI_F64 && prec != DSI_BF16 && prec != DSI_FP8_E4M3)
+    return fail(DSI_E_DTYPE, "unknown precision %d", (int)prec);
+  if ((prec == DSI_BF16 || prec == DSI_FP8_E4M3) && !paper)
+    return fail(DSI_E_DTYPE, "BF16/FP8 need the paper's architecture (C = 1,64,32,1; k = 11)");
+  if (prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "FP8 path not built in this version");
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  dsi_net *n = new (std::nothrow) dsi_net;
+  if (!n) return fail(DSI_E_NOMEM, "host allocation failed");
+  n->d = *desc;
+  n->prec = prec;
+  n->path = (paper && prec != DSI_F64) ? PATH_PAPER : PATH_GENERIC;
+  n->N = desc->n1 * desc->n2;
+  n->Mpad = prec == DSI_F64 ? desc->M : (desc->M + 15) / 16 * 16;
+  n->es = elem_size(prec);
+  for (int q = 0; q <= DSI_MAX_LAYERS; ++q) n->act_scale[q] = 1.0f;
+  const dsi_net_desc &d = *desc;
+  auto A = [&](void **p, size_t bytes) { return st == DSI_OK ? (st = alloc(p, bytes)) : st; };
+  A(&n->wfc, (size_t)n->N * n->Mpad * n->es);
+  if (n->path == PATH_GENERIC) {
+    for (int l = 0; l < d.L; ++l) {
+      A(&n->w[l], wcount(d, l) * n->es);
+      A(&n->b[l], bcount(d, l) * n->es);
+    }
+  } else {
+    A(&n->wp1, (size_t)11 * 2 * 64 * 8 * n->es);
+    A(&n->wp2, (size_t)64 * 32 * 121 * n->es);
+    A(&n->wp3, (size_t)32 * 121 * n->es);
+    for (int l = 0; l < 3; ++l) {
+      A((void **)&n->bp[l], bcount(d, l) * 4);
+      A((void **)&n->w32[l], wcount(d, l) * 4);
+      A((void **)&n->b32[l], bcount(d, l) * 4);
+    }
+  }
+  if (st == DSI_OK) st = pack_params(n, params, (hipStream_t)stream);
+  if (st == DSI_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)
+    st = fail(DSI_E_HIP, "packing failed: %s", hipGetErrorString(hipGetLastError()));
+  if (st != DSI_OK) {
+    free_net_buffers(n);
+    delete n;
+    return st;
+  }
+  *out = n;
+  return DSI_OK;
+}
+
+dsi_status dsi_net_update(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, void *stream) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  dsi_status st = check_params(net->d, params);
+  if (st != DSI_OK) return st;
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  return pack_params(net, params, (hipStream_t)stream);
+}
+
+dsi_status dsi_net_set_act_scales(dsi_net *net, const float *scales, int n) {
+  if (!net || !scales) return fail(DSI_E_NULL, "net and scales must be non-NULL");
+  if (net->prec != DSI_FP8_E4M3) return fail(DSI_E_STATE, "activation scales apply to FP8 nets only");
+  if (n != net->d.L + 1) return fail(DSI_E_SHAPE, "need %d scales", net->d.L + 1);
+  for (int q = 0; q < n; ++q) {
+    int e;
+    if (!(scales[q] > 0.0f) || std::frexp(scales[q], &e) != 0.5f)
+      return fail(DSI_E_SHAPE, "scale %d = %g is not a positive power of two", q, scales[q]);
+  }
+  for (int q = 0; q < n; ++q) net->act_scale[q] = scales[q];
+  return DSI_OK;
+}
+
+dsi_status dsi_net_free(dsi_ctx *ctx, dsi_net *net) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  (void)hipSetDevice(ctx->device);
+  (void)hipDeviceSynchronize();
+  free_net_buffers(net);
+  delete net;
+  return DSI_OK;
+}
+
+dsi_status dsi_net_info(const dsi_net *net, dsi_net_desc *desc, dsi_prec *prec) {
+  if (!net) return fail(DSI_E_NULL, "net is NULL");
+  if (desc) *desc = net->d;
+  if (prec) *prec = net->prec;
+  return DSI_OK;
+}
+
+dsi_status dsi_workspace_size(const dsi_net *net, int B, int train, size_t *bytes) {
+  if (!net || !bytes) return fail(DSI_E_NULL, "net and bytes must be non-NULL");
+  if (B < 0) return fail(DSI_E_SHAPE, "B = %d", B);
+  *bytes = layout(*net, B, train ? 1 : 0).end;
+  return DSI_OK;
+}
+
+dsi_status dsi_reserve(dsi_ctx *ctx, const dsi_net *net, int B, int train) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (B < 0) return fail(DSI_E_SHAPE, "B = %d", B);
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  size_t need = layout(*net, B, 0).end;
+  if (train) need = std::max(need, layout(*net, B, 1).end + backward_scratch_bytes(*net, B));
+  return ensure_ws(ctx, need);
+}
+
+dsi_status dsi_recover(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B, void *stream) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (B < 0) return fail(DSI_E_SHAPE, "B = %d", B);
+  if (B == 0) return DSI_OK;
+  if (!y || !xhat) return fail(DSI_E_NULL, "y and xhat must be non-NULL");
+  if (!aligned16(y) || !aligned16(xhat)) return fail(DSI_E_ALIGN, "y and xhat must be 16-byte aligned");
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  const Layout L = layout(*net, B, 0);
+  dsi_status st = ensure_ws(ctx, L.end);
+  if (st != DSI_OK) return st;
+  return forward_impl(ctx, net, y, xhat, B, ctx->ws, L, (hipStream_t)stream);
+}
+
+dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
+                             void *saved, size_t saved_bytes, void *stream) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1 for training", B);
+  if (!y || !xhat || !saved) return fail(DSI_E_NULL, "y, xhat and saved must be non-NULL");
+  if (!aligned16(y) || !aligned16(xhat) || !aligned16(saved)) return fail(DSI_E_ALIGN, "buffers must be 16-byte aligned");
+  const Layout L = layout(*net, B, 1);
+  if (saved_bytes < L.end) return fail(DSI_E_SHAPE, "saved buffer has %zu bytes, needs %zu", saved_bytes, L.end);
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  return forward_impl(ctx, net, y, xhat, B, saved, L, (hipStream_t)stream);
+}
+
+namespace {
+dsi_status check_grads(const dsi_net *net, const dsi_grads *g) {
+  if (!g) return fail(DSI_E_NULL, "grads is NULL");
+  for (int l = 0; l < net->d.L; ++l) {
+    if (!g->w[l] || !g->b[l]) return fail(DSI_E_NULL, "grads of layer %d are NULL", l);
+    if (!aligned16(g->w[l]) || !aligned16(g->b[l])) return fail(DSI_E_ALIGN, "grads of layer %d not aligned", l);
+  }
+  return DSI_OK;
+}
+
+dsi_status ensure_wfcT(dsi_net *n, hipStream_t s) {
+  if (n->wfcT || n->prec == DSI_F64) return DSI_OK;
+  // W_fc^T [M][N] fp32 from the packed copy [N][Mpad] (bf16 or fp32), via a host round trip
+  const size_t N = n->N, M = n->d.M, Mp = n->Mpad;
+  std::string host_in(N * Mp * n->es, '\0');
+  HIPCHK(hipStreamSynchronize(s));
+  HIPCHK(hipMemcpy(&host_in[0], n->wfc, host_in.size(), hipMemcpyDeviceToHost));
+  std::string host_out(N * M * 4, '\0');
+  float *o = reinterpret_cast<float *>(&host_out[0]);
+  for (size_t p = 0; p < N; ++p)
+    for (size_t m = 0; m < M; ++m) {
+      float v;
+      if (n->es == 2) {
+        uint16_t h;
+        memcpy(&h, &host_in[(p * Mp + m) * 2], 2);
+        uint32_t u = (uint32_t)h << 16;
+        memcpy(&v, &u, 4);
+      } else {
+        memcpy(&v, &host_in[(p * Mp + m) * 4], 4);
+      }
+      o[m * N + p] = v;
+    }
+  void *dst = nullptr;
+  dsi_status st = alloc(&dst, host_out.size());
+  if (st != DSI_OK) return st;
+  HIPCHK(hipMemcpy(dst, host_out.data(), host_out.size(), hipMemcpyHostToDevice));
+  n->wfcT = (float *)dst;
+  return DSI_OK;
+}
+}  // namespace
+
+dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, const void *saved,
+                        size_t saved_bytes, int B, const dsi_grads *grads, float *gy, void *stream) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
+  if (!gxhat || !saved) return fail(DSI_E_NULL, "gxhat and saved must be non-NULL");
+  dsi_status st = check_grads(net, grads);
+  if (st != DSI_OK) return st;
+  const Layout L = layout(*net, B, 1);
+  if (saved_bytes < L.end) return fail(DSI_E_SHAPE, "saved buffer has %zu bytes, needs %zu", saved_bytes, L.end);
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  if (gy && (st = ensure_wfcT(const_cast<dsi_net *>(net), s)) != DSI_OK) return st;
+  const size_t scratch = backward_scratch_bytes(*net, B);
+  if ((st = ensure_ws(ctx, scratch)) != DSI_OK) return st;
+  const dsi_net_desc &d = net->d;
+  const int N = net->N;
+  // gz of the last layer: gxhat masked by the last ReLU, in the path's gradient precision
+  const size_t gz_off = scratch - rnd((size_t)B * N * (net->prec == DSI_F64 ? 8 : 4)) - rnd((size_t)B * 4 * 8) - 256;
+  void *gz = at<char>(ctx->ws, gz_off);
+  const void *last = at<char>(const_cast<void *>(saved), L.act[d.L]);
+  const long n = (long)B * N;
+  if (net->prec == DSI_F64)
+    HIPCHK(dsi::relu_mask_f64(gxhat, d.relu_last ? (const double *)last : nullptr, (double *)gz, n, s));
+  else
+    HIPCHK(dsi::relu_mask_f32(gxhat, d.relu_last ? (const float *)last : nullptr, (float *)gz, n, s));
+  return backward_impl(ctx, net, gz, saved, L, B, grads, gy, ctx->ws, s);
+}
+
+dsi_status dsi_set_stage_timing(dsi_ctx *ctx, int enable) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  ctx->timing = enable ? 1 : 0;
+  return DSI_OK;
+}
+
+dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls) {
+  if (!ctx || !ms || !calls) return fail(DSI_E_NULL, "ctx, ms and calls must be non-NULL");
+  if (nstages < 1) return fail(DSI_E_SHAPE, "nstages = %d", nstages);
+  for (int k = 0; k < nstages; ++k) ms[k] = 0.0;
+  int n = 0;
+  for (auto &set : ctx->ev) {
+    if (set.empty()) continue;
+    if (hipEventSynchronize(set.back()) != hipSuccess) return fail(DSI_E_HIP, "event synchronize failed");
+    for (size_t k = 0; k + 1 < set.size() && (int)k < nstages; ++k) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, set[k], set[k + 1]) == hipSuccess) ms[k] += t;
+    }
+    for (hipEvent_t e : set) (void)hipEventDestroy(e);
+    ++n;
+  }
+  ctx->ev.clear();
+  *calls = n;
+  return DSI_OK;
+}
+
+dsi_status dsi_metrics(dsi_ctx *ctx, const float *xhat, const float *x, int B, int N, double *out, void *stream) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  if (B < 0 || N < 1) return fail(DSI_E_SHAPE, "bad sizes B=%d N=%d", B, N);
+  if (B == 0) return DSI_OK;
+  if (!xhat || !x || !out) return fail(DSI_E_NULL, "xhat, x, out must be non-NULL");
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  HIPCHK(dsi::image_stats_f32(xhat, x, B, N, out, nullptr, 0.0, 0, (hipStream_t)stream));
+  return DSI_OK;
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ loss gradient and training
+namespace {
+// forward (into saved = ws head), loss, dL/dxhat, backward; gradients into g.
+dsi_status loss_grad_impl(dsi_ctx *ctx, dsi_net *net, const float *y, const float *x, int B, const dsi_grads *g,
+                          float *gy, double *loss_dev, hipStream_t s) {
+  const dsi_net_desc &d = net->d;
+  const int N = net->N;
+  const Layout L = layout(*net, B, 1);
+  const size_t scratch = backward_scratch_bytes(*net, B);
+  dsi_status st;
+  if (gy && (st = ensure_wfcT(net, s)) != DSI_OK) return st;
+  if ((st = ensure_ws(ctx, L.end + scratch)) != DSI_OK) return st;
+  void *saved = ctx->ws;
+  void *scr = at<char>(ctx->ws, L.end);
+  const size_t gz_off = scratch - rnd((size_t)B * N * (net->prec == DSI_F64 ? 8 : 4)) - rnd((size_t)B * 4 * 8) - 256;
+  void *gz = at<char>(scr, gz_off);
+  double *stats = at<double>(scr, gz_off + rnd((size_t)B * N * (net->prec == DSI_F64 ? 8 : 4)));
+  double *loss_tmp = at<double>(scr, scratch - 256);
+  if ((st = forward_impl(ctx, net, y, nullptr, B, saved, L, s)) != DSI_OK) return st;
+  const double scale = 2.0 / B;
+  if (net->prec == DSI_F64) {
+    HIPCHK(dsi::image_stats_f64(at<double>(saved, L.act[d.L]), x, B, N, stats, (double *)gz, scale, d.relu_last, s));
+  } else {
+    HIPCHK(dsi::image_stats_f32(at<float>(saved, L.act[d.L]), x, B, N, stats, (float *)gz, scale, d.relu_last, s));
+  }
+  HIPCHK(dsi::loss_sum(stats, B, loss_dev ? loss_dev : loss_tmp, s));
+  return backward_impl(ctx, net, gz, saved, L, B, g, gy, scr, s);
+}
+}  // namespace
+
+extern "C" {
+
+dsi_status dsi_loss_grad(dsi_ctx *ctx, dsi_net *net, const float *y, const float *x, int B, const dsi_grads *grads,
+                         float *gy, double *loss_dev, void *stream) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
+  if (!y || !x) return fail(DSI_E_NULL, "y and x must be non-NULL");
+  if (!aligned16(y) || !aligned16(x)) return fail(DSI_E_ALIGN, "y and x must be 16-byte aligned");
+  dsi_status st = check_grads(net, grads);
+  if (st != DSI_OK) return st;
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  return loss_grad_impl(ctx, net, y, x, B, grads, gy, loss_dev, (hipStream_t)stream);
+}
+
+dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, dsi_adam *opt, const float *y,
+                          const float *x, int B, float lr, double *loss_dev, void *stream) {
+  if (!ctx || !net || !opt) return fail(DSI_E_NULL, "ctx, net and opt must be non-NULL");
+  if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
+  if (!y || !x) return fail(DSI_E_NULL, "y and x must be non-NULL");
+  dsi_status st = check_params(net->d, params);
+  if (st != DSI_OK) return st;
+  const dsi_net_desc &d = net->d;
+  for (int l = 0; l < d.L; ++l)
+    if (!opt->m_w[l] || !opt->v_w[l] || !opt->m_b[l] || !opt->v_b[l]) return fail(DSI_E_NULL, "Adam state of layer %d is NULL", l);
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  // gradient buffers live after the training workspace
+  const Layout L = layout(*net, B, 1);
+  const size_t scratch = backward_scratch_bytes(*net, B);
+  size_t gbytes = 0;
+  for (int l = 0; l < d.L; ++l) gbytes += rnd(wcount(d, l) * 4) + rnd(bcount(d, l) * 4);
+  if ((st = ensure_ws(ctx, L.end + scratch + gbytes)) != DSI_OK) return st;
+  dsi_grads g{};
+  size_t off = L.end + scratch;
+  for (int l = 0; l < d.L; ++l) {
+    g.w[l] = at<float>(ctx->ws, off); off += rnd(wcount(d, l) * 4);
+    g.b[l] = at<float>(ctx->ws, off); off += rnd(bcount(d, l) * 4);
+  }
+  if ((st = loss_grad_impl(ctx, net, y, x, B, &g, nullptr, loss_dev, s)) != DSI_OK) return st;
+  const long t = opt->step + 1;
+  const float c1 = (float)(1.0 - std::pow((double)opt->beta1, (double)t));
+  const float c2 = (float)(1.0 - std::pow((double)opt->beta2, (double)t));
+  for (int l = 0; l < d.L; ++l) {
+    HIPCHK(dsi::adam_f32(params->w[l], g.w[l], opt->m_w[l], opt->v_w[l], wcount(d, l), lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
+    HIPCHK(dsi::adam_f32(params->b[l], g.b[l], opt->m_b[l], opt->v_b[l], bcount(d, l), lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
+  }
+  opt->step = t;
+  return pack_params(net, params, s);
+}
+
+}  // extern "C"

@@ -1,0 +1,345 @@
+// conv_mfma.hip -- Eq. (1) layers of the paper's network (Sec. 5: 1 -> 64 -> 32
+// -> 1 channels, 11 x 11 filters) as implicit GEMMs on CDNA4 matrix cores.
+//
+// Activation layout in HBM: channel-blocked [B][C/16][H][W][16] ("16-channel
+// slices"), so one slice of a tile is a dense 2-D block of 32-byte (bf16) or
+// 64-byte (fp32) pixels.  Weights are pre-packed in MFMA fragment order, so a
+// wave loads a 32 x 16 weight fragment as one coalesced 1 KiB (bf16) read.
+//
+// conv_mid  (Cin % 16 == 0 -> Cout 32 or 64): the hot loop.  A wave owns
+//   ROWS output rows x 32 columns x Cout channels.  For each 16-channel slice
+//   and horizontal tap v it keeps the 11 vertical-tap weight fragments in
+//   registers and walks the ROWS+10 input rows of its halo once: every
+//   activation fragment read from LDS feeds up to 11 MFMAs (one per output
+//   row it reaches), so LDS traffic is ~1/5 of a naive implicit GEMM.
+//   MFMA: A = weights (32 out-channels x 16 in-channels), B = activations
+//   (16 in-channels x 32 pixels), D = 32 out-channels x 32 pixels.
+// conv_first (Cin = 1 -> 64): K = taps; one MFMA k-step per filter row u,
+//   its 16 K slots holding taps v = 0..10 (5 zero slots), gathered from a
+//   small LDS tile of the proxy image.
+// conv_last  (Cin = 32 -> 1): a degenerate GEMM (one output channel), done on
+//   the vector ALUs with packed bf16 dot products.
+#include "common.h"
+#include "internal.h"
+
+namespace dsi {
+
+constexpr int KT = 11;   // filter size of the paper's layers
+constexpr int RAD = 5;   // (KT - 1) / 2
+
+// ----------------------------------------------------------------- LDS helpers
+// Slice tiles live in LDS as [row][chunk][col] 16-byte units, so the 32 lanes
+// of a half-wave read 32 consecutive units (conflict-free).
+template <typename T> DSI_INLINE Frag8<T> lds_frag(const unsigned char *base, int plane_bytes);
+template <> DSI_INLINE Frag8<bf16> lds_frag<bf16>(const unsigned char *p, int) {
+  Frag8<bf16> f;
+  f.v = *reinterpret_cast<const bf16x8 *>(p);
+  return f;
+}
+template <> DSI_INLINE Frag8<float> lds_frag<float>(const unsigned char *p, int plane) {
+  Frag8<float> f;
+  f.lo = *reinterpret_cast<const f32x4 *>(p);
+  f.hi = *reinterpret_cast<const f32x4 *>(p + plane);
+  return f;
+}
+
+template <typename TO> DSI_INLINE void store4(TO *dst, float a, float b, float c, float d);
+template <> DSI_INLINE void store4<float>(float *dst, float a, float b, float c, float d) {
+  *reinterpret_cast<f32x4 *>(dst) = f32x4{a, b, c, d};
+}
+template <> DSI_INLINE void store4<bf16>(bf16 *dst, float a, float b, float c, float d) {
+  bf16x4 v;
+  v[0] = (bf16)a; v[1] = (bf16)b; v[2] = (bf16)c; v[3] = (bf16)d;
+  *reinterpret_cast<bf16x4 *>(dst) = v;
+}
+template <typename T> DSI_INLINE void load4f(const T *src, float *o);
+template <> DSI_INLINE void load4f<float>(const float *src, float *o) {
+  f32x4 v = *reinterpret_cast<const f32x4 *>(src);
+  o[0] = v[0]; o[1] = v[1]; o[2] = v[2]; o[3] = v[3];
+}
+template <> DSI_INLINE void load4f<bf16>(const bf16 *src, float *o) {
+  bf16x4 v = *reinterpret_cast<const bf16x4 *>(src);
+  o[0] = (float)v[0]; o[1] = (float)v[1]; o[2] = (float)v[2]; o[3] = (float)v[3];
+}
+
+// ===================================================================== conv_mid
+// in   [B][CIN/16][H][W][16]  (T)
+// wp   [CIN/16][11 v][11 u][COUT/32][64 lanes][8]  (T): lane l holds
+//      W[co = ct*32 + l%32][ci = cs*16 + (l/32)*8 + e][u][v]
+// EPI_BIAS: out = ReLU?(acc + bias); bias per pixel [H][W][COUT] or per channel [COUT] (fp32)
+// EPI_MASK: out = acc * (mask > 0), mask in the output layout (backward through ReLU)
+template <typename T, int CIN, int COUT, int ROWS, int EPI, typename TO>
+__global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in, const T *__restrict__ wp,
+                                                       const float *__restrict__ bias, int bias_pp, int relu,
+                                                       const T *__restrict__ mask, TO *__restrict__ out,
+                                                       int H, int W, int tiles_w, int tiles_per_img) {
+  constexpr int TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
+  constexpr int CH16 = (int)sizeof(T);       // 16-byte chunks per pixel per slice: bf16 2, fp32 4
+  constexpr int NCT = COUT / 32, NCS = CIN / 16;
+  constexpr int PLANE = LW * 16;              // bytes between chunk planes of one LDS row
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * CH16 * PLANE];
+
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
+  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
+
+  f32x16 acc[ROWS][NCT];
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[i][c][r] = 0.0f;
+
+  for (int cs = 0; cs < NCS; ++cs) {
+    __syncthreads();  // previous slice fully consumed
+    const T *src = in + (long)(img * NCS + cs) * H * W * 16;
+    for (int idx = tid; idx < LH * LW * CH16; idx += 256) {
+      const int chunk = idx / (LH * LW), pix = idx - chunk * (LH * LW);
+      const int row = pix / LW, col = pix - row * LW;
+      const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+      i32x4 val = {0, 0, 0, 0};
+      if (gi >= 0 && gi < H && gj >= 0 && gj < W)
+        val = *reinterpret_cast<const i32x4 *>(src + ((long)gi * W + gj) * 16 + chunk * (16 / (int)sizeof(T)));
+      *reinterpret_cast<i32x4 *>(lds + (row * CH16 + chunk) * PLANE + col * 16) = val;
+    }
+    __syncthreads();
+    const T *wcs = wp + (long)cs * KT * KT * NCT * 512 + lane * 8;
+    for (int v = 0; v < KT; ++v) {
+      Frag8<T> wf[KT][NCT];
+#pragma unroll
+      for (int u = 0; u < KT; ++u)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + ((v * KT + u) * NCT + c) * 512);
+      const unsigned char *lrow = lds + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + (px + v) * 16;
+#pragma unroll
+      for (int rr = 0; rr < ROWS + 2 * RAD; ++rr) {
+        Frag8<T> xf = lds_frag<T>(lrow + rr * CH16 * PLANE, PLANE);
+#pragma unroll
+        for (int u = 0; u < KT; ++u) {
+          const int i = rr - u;  // output row (within the wave) that input row rr reaches through tap u
+          if (i >= 0 && i < ROWS) {
+#pragma unroll
+            for (int c = 0; c < NCT; ++c) wf[u][c].mma(xf, acc[i][c]);
+          }
+        }
+      }
+    }
+  }
+
+  // epilogue: lane holds pixel (row i, col px), channels ct*32 + 8q + 4h + e
+  const int gj = bj0 + px;
+#pragma unroll
+  for (int i = 0; i < ROWS; ++i) {
+    const int gi = bi0 + wave * ROWS + i;
+    if (gi >= H || gj >= W) continue;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int co0 = c * 32 + 8 * q + 4 * h;
+        const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
+        float vals[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vals[e] = acc[i][c][4 * q + e];
+        if constexpr (EPI == EPI_BIAS) {
+          float bv[4];
+          load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            vals[e] += bv[e];
+            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+          }
+        } else {
+          float mv[4];
+          load4f<T>(mask + o, mv);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) vals[e] = mv[e] > 0.0f ? vals[e] : 0.0f;
+        }
+        store4<TO>(out + o, vals[0], vals[1], vals[2], vals[3]);
+      }
+  }
+}
+
+// =================================================================== conv_first
+// in  [B][H][W] (T), wp [11 u][COUT/32][64][8] (T): lane l holds
+//     W[co = ct*32 + l%32][0][u][v = 8*(l/32) + e] (0 for v >= 11)
+// out [B][COUT/16][H][W][16] (T)
+template <typename T, int COUT>
+__global__ __launch_bounds__(256) void conv_first_kernel(const T *__restrict__ in, const T *__restrict__ wp,
+                                                         const float *__restrict__ bias, int bias_pp,
+                                                         T *__restrict__ out, int H, int W, int tiles_w,
+                                                         int tiles_per_img) {
+  constexpr int ROWS = 4, TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
+  constexpr int NCT = COUT / 32;
+  __shared__ T tile[LH * LW + 16];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
+  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
+  const T *src = in + (long)img * H * W;
+  for (int idx = tid; idx < LH * LW; idx += 256) {
+    const int row = idx / LW, col = idx - row * LW;
+    const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+    tile[idx] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? src[(long)gi * W + gj] : from_f32<T>(0.0f);
+  }
+  if (tid < 16) tile[LH * LW + tid] = from_f32<T>(0.0f);
+  __syncthreads();
+
+  Frag8<T> wf[KT][NCT];
+#pragma unroll
+  for (int u = 0; u < KT; ++u)
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wp + ((u * NCT + c) * 64 + lane) * 8);
+
+  const int gj = bj0 + px;
+  for (int ri = 0; ri < ROWS; ++ri) {
+    const int lr = wave * ROWS + ri;
+    f32x16 acc[NCT];
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
+      const T *p = tile + (lr + u) * LW + px + 8 * h;
+      float xs[8];
+#pragma unroll
+      for (int e = 0; e < 8; ++e) xs[e] = (8 * h + e < KT) ? to_f32(p[e]) : 0.0f;
+      Frag8<T> xf = frag_from<T>(xs);
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) wf[u][c].mma(xf, acc[c]);
+    }
+    const int gi = bi0 + lr;
+    if (gi >= H || gj >= W) continue;
+#pragma unroll
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const int co0 = c * 32 + 8 * q + 4 * h;
+        float bv[4];
+        load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
+        float vals[4];
+#pragma unroll
+        for (int e = 0; e < 4; ++e) vals[e] = fmaxf(acc[c][4 * q + e] + bv[e], 0.0f);
+        const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
+        store4<T>(out + o, vals[0], vals[1], vals[2], vals[3]);
+      }
+  }
+}
+
+// ==================================================================== conv_last
+// in [B][CIN/16][H][W][16] (T), w [CIN/16][11 u][11 v][16] (T, plain), out [B][H][W] fp32.
+// A thread computes 2 horizontally adjacent pixels; 16 x 16 threads cover 16 x 32.
+template <typename T> DSI_INLINE float dot16(const T *x, const T *w);
+template <> DSI_INLINE float dot16<bf16>(const bf16 *x, const bf16 *w) {
+  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
+  const bf16x2_t *xa = reinterpret_cast<const bf16x2_t *>(x);
+  const bf16x2_t *wa = reinterpret_cast<const bf16x2_t *>(w);
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 8; ++q) s = __builtin_amdgcn_fdot2_f32_bf16(xa[q], wa[q], s, false);
+  return s;
+}
+template <> DSI_INLINE float dot16<float>(const float *x, const float *w) {
+  float s = 0.0f;
+#pragma unroll
+  for (int q = 0; q < 16; ++q) s = fmaf(x[q], w[q], s);
+  return s;
+}
+
+template <typename T, int CIN>
+__global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in, const T *__restrict__ w,
+                                                        const float *__restrict__ bias, int bias_pp, int relu,
+                                                        float *__restrict__ out, int H, int W, int tiles_w,
+                                                        int tiles_per_img) {
+  constexpr int TH = 16, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD, NCS = CIN / 16;
+  __shared__ __attribute__((aligned(16))) T tile[LH * LW * 16];
+  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
+  constexpr int PER16 = 16 / (int)sizeof(T) * 1;  // elements per 16-byte unit
+  float acc0 = 0.0f, acc1 = 0.0f;
+  for (int cs = 0; cs < NCS; ++cs) {
+    __syncthreads();
+    const T *src = in + (long)(img * NCS + cs) * H * W * 16;
+    constexpr int UPP = 16 / PER16;  // 16-byte units per pixel
+    for (int idx = tid; idx < LH * LW * UPP; idx += 256) {
+      const int pix = idx / UPP, part = idx - pix * UPP;
+      const int row = pix / LW, col = pix - row * LW;
+      const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+      i32x4 val = {0, 0, 0, 0};
+      if (gi >= 0 && gi < H && gj >= 0 && gj < W)
+        val = *reinterpret_cast<const i32x4 *>(src + ((long)gi * W + gj) * 16 + part * PER16);
+      *reinterpret_cast<i32x4 *>(tile + pix * 16 + part * PER16) = val;
+    }
+    __syncthreads();
+    const T *wcs = w + (long)cs * KT * KT * 16;
+    for (int u = 0; u < KT; ++u) {
+      const T *lrow = tile + ((ty + u) * LW + 2 * tx) * 16;
+#pragma unroll
+      for (int v = 0; v < KT; ++v) {
+        const T *wv = wcs + (u * KT + v) * 16;  // uniform across the block
+        acc0 += dot16<T>(lrow + v * 16, wv);
+        acc1 += dot16<T>(lrow + (v + 1) * 16, wv);
+      }
+    }
+  }
+  const int gi = bi0 + ty, gj = bj0 + 2 * tx;
+  if (gi >= H) return;
+  float *o = out + ((long)img * H + gi) * W;
+  if (gj < W) {
+    float v = acc0 + (bias_pp ? bias[(long)gi * W + gj] : bias[0]);
+    o[gj] = relu ? fmaxf(v, 0.0f) : v;
+  }
+  if (gj + 1 < W) {
+    float v = acc1 + (bias_pp ? bias[(long)gi * W + gj + 1] : bias[0]);
+    o[gj + 1] = relu ? fmaxf(v, 0.0f) : v;
+  }
+}
+
+// ==================================================================== launchers
+static inline void tiles(int H, int W, int TH, int TW, int &tw, int &tpi) {
+  tw = (W + TW - 1) / TW;
+  tpi = tw * ((H + TH - 1) / TH);
+}
+
+template <typename T>
+hipError_t conv_first(const T *in, const T *wp, const float *bias, int bias_pp, T *out, int B, int H,
+                      int W, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  int tw, tpi;
+  tiles(H, W, 16, 32, tw, tpi);
+  conv_first_kernel<T, 64><<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, out, H, W, tw, tpi);
+  return hipGetLastError();
+}
+
+template <typename T, int CIN, int COUT, int EPI, typename TO>
+hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
+                    TO *out, int B, int H, int W, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  constexpr int ROWS = COUT == 32 ? 8 : 4;
+  int tw, tpi;
+  tiles(H, W, 4 * ROWS, 32, tw, tpi);
+  conv_mid_kernel<T, CIN, COUT, ROWS, EPI, TO>
+      <<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, int relu, float *out, int B,
+                     int H, int W, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  int tw, tpi;
+  tiles(H, W, 16, 32, tw, tpi);
+  conv_last_kernel<T, 32><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
+  return hipGetLastError();
+}
+
+template hipError_t conv_first<bf16>(const bf16 *, const bf16 *, const float *, int, bf16 *, int, int, int, hipStream_t);
+template hipError_t conv_first<float>(const float *, const float *, const float *, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_mid<bf16, 64, 32, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
+template hipError_t conv_mid<float, 64, 32, EPI_BIAS, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
+template hipError_t conv_last<bf16>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_last<float>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
+
+}  // namespace dsi

@@ -1,0 +1,139 @@
+// gemm.hip -- the dense layers of the recovery path on MFMA.
+//
+//   measurement  y  = Phi x      : y[b][m]  = sum_n Phi[m][n]  x[b][n]   (Sec. 1)
+//   proxy        x~ = Phi^T y    : x~[b][p] = sum_m Wfc[p][m]  y[b][m]   (Sec. 4)
+//   proxy grad   dy = Wfc^T dx~  : dy[b][m] = sum_p WfcT[m][p] dx~[b][p]
+//
+// All three are C[b][o] = sum_k X[b][k] W[o][k] with both operands
+// K-contiguous ("NT").  A wave owns a 32 (b) x 32 (o) tile of C; the four
+// waves of a block cover 64 x 64.  MFMA A = X rows, B = W rows, so a lane
+// holds C[b0 + row(r)][o0 + lane%32] and stores are 128-byte coalesced runs.
+// The FC is HBM-bound below ~300 images per batch (W is streamed once per
+// 32 images from L2) and MFMA-bound above.
+#include "common.h"
+#include "internal.h"
+
+namespace dsi {
+
+// 8 consecutive K values of row `row` starting at k (zero beyond K), as float.
+template <typename TS>
+DSI_INLINE void load8_checked(const TS *base, long ld, int row, int k, int K, float *out) {
+  const TS *p = base + (long)row * ld + k;
+#pragma unroll
+  for (int e = 0; e < 8; ++e) out[e] = (k + e < K) ? to_f32(p[e]) : 0.0f;
+}
+
+template <typename TS, typename TM> struct Loader;
+// fast path: rows padded to a multiple of 16 elements, 16-byte aligned
+template <> struct Loader<bf16, bf16> {
+  static DSI_INLINE Frag8<bf16> ld(const bf16 *p) { return frag_load<bf16>(p); }
+};
+template <> struct Loader<float, float> {
+  static DSI_INLINE Frag8<float> ld(const float *p) { return frag_load<float>(p); }
+};
+template <> struct Loader<float, bf16> {
+  static DSI_INLINE Frag8<bf16> ld(const float *p) {
+    f32x4 a = *reinterpret_cast<const f32x4 *>(p), b = *reinterpret_cast<const f32x4 *>(p + 4);
+    float x[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
+    return frag_from<bf16>(x);
+  }
+};
+template <> struct Loader<bf16, float> {
+  static DSI_INLINE Frag8<float> ld(const bf16 *p) {
+    bf16x8 v = *reinterpret_cast<const bf16x8 *>(p);
+    float x[8];
+#pragma unroll
+    for (int e = 0; e < 8; ++e) x[e] = (float)v[e];
+    return frag_from<float>(x);
+  }
+};
+
+// C[b][o] = scale * sum_k X[b][k] W[o][k];  X [Bn][ldx] (TX), W [O][ldw] (TW), C [Bn][ldc] (TC).
+// VEC: K % 16 == 0, ldx/ldw multiples of 8, pointers 16-byte aligned.
+template <typename TX, typename TW, typename TC, typename TM, bool VEC>
+__global__ __launch_bounds__(256) void gemm_nt_kernel(const TX *__restrict__ X, long ldx,
+                                                      const TW *__restrict__ W, long ldw,
+                                                      TC *__restrict__ C, long ldc, int Bn, int O,
+                                                      int K, float scale) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int o0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (b0 >= Bn || o0 >= O) return;
+  const int rb = min(b0 + (lane & 31), Bn - 1);  // clamp rows: loads stay in bounds
+  const int ro = min(o0 + (lane & 31), O - 1);
+  const int kh = (lane >> 5) * 8;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  if constexpr (VEC) {
+    const TX *px = X + (long)rb * ldx + kh;
+    const TW *pw = W + (long)ro * ldw + kh;
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      Frag8<TM> fx = Loader<TX, TM>::ld(px + k0);
+      Frag8<TM> fw = Loader<TW, TM>::ld(pw + k0);
+      fx.mma(fw, acc);
+    }
+  } else {
+    for (int k0 = 0; k0 < K; k0 += 16) {
+      float xs[8], ws[8];
+      load8_checked(X, ldx, rb, k0 + kh, K, xs);
+      load8_checked(W, ldw, ro, k0 + kh, K, ws);
+      Frag8<TM> fx = frag_from<TM>(xs), fw = frag_from<TM>(ws);
+      fx.mma(fw, acc);
+    }
+  }
+  const int o = o0 + (lane & 31);
+  if (o >= O) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = b0 + mfma_row(lane, r);
+    if (b < Bn) C[(long)b * ldc + o] = from_f32<TC>(acc[r] * scale);
+  }
+}
+
+// FP64 reference-precision variant (VALU), for the DSI_F64 checking path.
+__global__ __launch_bounds__(256) void gemm_nt_f64_kernel(const double *__restrict__ X, long ldx,
+                                                          const double *__restrict__ W, long ldw,
+                                                          double *__restrict__ C, long ldc, int Bn,
+                                                          int O, int K) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)Bn * O) return;
+  const int b = (int)(idx / O), o = (int)(idx % O);
+  double s = 0.0;
+  for (int k = 0; k < K; ++k) s += X[(long)b * ldx + k] * W[(long)o * ldw + k];
+  C[(long)b * ldc + o] = s;
+}
+
+template <typename TX, typename TW, typename TC, typename TM>
+hipError_t launch_gemm(const TX *X, long ldx, const TW *W, long ldw, TC *C, long ldc, int Bn, int O,
+                       int K, bool vec, float scale, hipStream_t s) {
+  if (Bn <= 0 || O <= 0) return hipSuccess;
+  dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
+  if (vec)
+    gemm_nt_kernel<TX, TW, TC, TM, true><<<grid, 256, 0, s>>>(X, ldx, W, ldw, C, ldc, Bn, O, K, scale);
+  else
+    gemm_nt_kernel<TX, TW, TC, TM, false><<<grid, 256, 0, s>>>(X, ldx, W, ldw, C, ldc, Bn, O, K, scale);
+  return hipGetLastError();
+}
+
+hipError_t gemm_nt_f32(const float *X, long ldx, const float *W, long ldw, float *C, long ldc,
+                       int Bn, int O, int K, bool vec, hipStream_t s) {
+  return launch_gemm<float, float, float, float>(X, ldx, W, ldw, C, ldc, Bn, O, K, vec, 1.0f, s);
+}
+hipError_t gemm_nt_bf16_out_bf16(const float *X, long ldx, const bf16 *W, long ldw, bf16 *C,
+                                 long ldc, int Bn, int O, int K, bool vec, hipStream_t s) {
+  return launch_gemm<float, bf16, bf16, bf16>(X, ldx, W, ldw, C, ldc, Bn, O, K, vec, 1.0f, s);
+}
+hipError_t gemm_nt_bf16_out_f32(const float *X, long ldx, const bf16 *W, long ldw, float *C,
+                                long ldc, int Bn, int O, int K, bool vec, hipStream_t s) {
+  return launch_gemm<float, bf16, float, bf16>(X, ldx, W, ldw, C, ldc, Bn, O, K, vec, 1.0f, s);
+}
+hipError_t gemm_nt_f64(const double *X, long ldx, const double *W, long ldw, double *C, long ldc,
+                       int Bn, int O, int K, hipStream_t s) {
+  if (Bn <= 0 || O <= 0) return hipSuccess;
+  const long n = (long)Bn * O;
+  gemm_nt_f64_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(X, ldx, W, ldw, C, ldc, Bn, O, K);
+  return hipGetLastError();
+}
+
+}  // namespace dsi

@@ -1,0 +1,71 @@
+// internal.h -- launchers shared between the kernel files and the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace dsi {
+
+// Activation tensor view: planar [B][C][H][W] or channel-blocked [B][C/16][H][W][16].
+struct ActView {
+  int C, H, W;
+  int blocked;
+};
+
+enum { EPI_BIAS = 0, EPI_MASK = 1 };
+
+// gemm.hip: C[b][o] = sum_k X[b][k] W[o][k]
+hipError_t gemm_nt_f32(const float *X, long ldx, const float *W, long ldw, float *C, long ldc,
+                       int Bn, int O, int K, bool vec, hipStream_t s);
+hipError_t gemm_nt_bf16_out_bf16(const float *X, long ldx, const __bf16 *W, long ldw, __bf16 *C,
+                                 long ldc, int Bn, int O, int K, bool vec, hipStream_t s);
+hipError_t gemm_nt_bf16_out_f32(const float *X, long ldx, const __bf16 *W, long ldw, float *C,
+                                long ldc, int Bn, int O, int K, bool vec, hipStream_t s);
+hipError_t gemm_nt_f64(const double *X, long ldx, const double *W, long ldw, double *C, long ldc,
+                       int Bn, int O, int K, hipStream_t s);
+
+// conv_direct.hip (any shape)
+template <typename TI, typename TW, typename TO, typename Acc>
+hipError_t conv_fwd_direct(const TI *in, ActView vi, const TW *w, const TW *bias, int bias_pp,
+                           int relu, TO *out, ActView vo, int B, int k, hipStream_t s);
+template <typename TG, typename TW, typename TA, typename TO, typename Acc>
+hipError_t conv_dgrad_direct(const TG *gz, ActView vg, const TW *w, const TA *amask, ActView va,
+                             TO *gin, ActView vo, int B, int k, hipStream_t s);
+template <typename TG, typename TI, typename Acc, typename TD>
+hipError_t conv_wgrad_direct(const TG *gz, ActView vg, const TI *in, ActView vi, int B, int k,
+                             TD *dw, hipStream_t s);
+template <typename TG, typename Acc, typename TD>
+hipError_t bias_grad(const TG *gz, ActView vg, int B, int per_pixel, TD *db, hipStream_t s);
+
+// conv_mfma.hip (the paper's 1 -> 64 -> 32 -> 1, 11 x 11 network)
+template <typename T>
+hipError_t conv_first(const T *in, const T *wp, const float *bias, int bias_pp, T *out, int B, int H,
+                      int W, hipStream_t s);
+template <typename T, int CIN, int COUT, int EPI, typename TO>
+hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
+                    TO *out, int B, int H, int W, hipStream_t s);
+template <typename T>
+hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, int relu, float *out, int B,
+                     int H, int W, hipStream_t s);
+
+}  // namespace dsi
+
+namespace dsi {
+// misc.hip; prec: 0 = fp32, 1 = bf16
+hipError_t pack_fc(const float *w, void *out, int N, int M, int Mpad, int prec, hipStream_t s);
+hipError_t pack_mid(const float *w, void *out, int CIN, int COUT, int flip, int prec, hipStream_t s);
+hipError_t pack_first(const float *w, void *out, int prec, hipStream_t s);
+hipError_t pack_last(const float *w, void *out, int CIN, int prec, hipStream_t s);
+hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s);
+hipError_t cast_f32_f64(const float *in, double *out, long n, hipStream_t s);
+hipError_t cast_f64_f32(const double *in, float *out, long n, hipStream_t s);
+hipError_t pad_rows(const float *in, void *out, int B, int M, int Mpad, int prec, hipStream_t s);
+hipError_t image_stats_f32(const float *xh, const float *x, int B, int N, double *stats, float *g,
+                           double scale, int relu_last, hipStream_t s);
+hipError_t image_stats_f64(const double *xh, const float *x, int B, int N, double *stats, double *g64,
+                           double scale, int relu_last, hipStream_t s);
+hipError_t loss_sum(const double *stats, int B, double *loss, hipStream_t s);
+hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hipStream_t s);
+hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, hipStream_t s);
+hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s);
+}  // namespace dsi

@@ -1,0 +1,230 @@
+// misc.hip -- weight packing, casts, the loss and its gradient, Sec. 5
+// metrics, and the Adam update (Kingma & Ba).
+#include "common.h"
+#include "internal.h"
+
+namespace dsi {
+
+#define GRID1(n) (unsigned)(((long)(n) + 255) / 256), 256
+
+// ------------------------------------------------------------- packing
+// W_fc [N][M] fp32 -> [N][Mpad] T, zero-padded columns (K of the proxy GEMM).
+template <typename T>
+__global__ void pack_fc_kernel(const float *__restrict__ w, T *__restrict__ out, int N, int M, int Mpad) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)N * Mpad) return;
+  const int p = (int)(idx / Mpad), m = (int)(idx % Mpad);
+  out[idx] = from_f32<T>(m < M ? w[(long)p * M + m] : 0.0f);
+}
+
+// conv_mid weights: W [COUT][CIN][11][11] -> [CIN/16][11 v][11 u][COUT/32][64][8].
+// flip = 1 packs the data-gradient operator instead: W'[ci][co][u][v] = W[co][ci][10-u][10-v]
+// (so COUT/CIN below are those of the operator being packed).
+template <typename T>
+__global__ void pack_mid_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN, int COUT, int flip) {
+  const long n = (long)CIN * COUT * 121;
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
+  long rest = idx >> 9;
+  const int nct = COUT / 32;
+  const int ct = (int)(rest % nct); rest /= nct;
+  const int u = (int)(rest % 11); rest /= 11;
+  const int v = (int)(rest % 11); rest /= 11;
+  const int cs = (int)rest;
+  const int co = ct * 32 + (lane & 31), ci = cs * 16 + (lane >> 5) * 8 + e;
+  float val;
+  if (!flip) val = w[(((long)co * CIN + ci) * 11 + u) * 11 + v];
+  else val = w[(((long)ci * COUT + co) * 11 + (10 - u)) * 11 + (10 - v)];  // original W[ci][co] (its Cout = CIN here)
+  out[idx] = from_f32<T>(val);
+}
+
+// conv_first weights: W [64][1][11][11] -> [11 u][2 ct][64][8], taps v = 8*(lane/32) + e.
+template <typename T>
+__global__ void pack_first_kernel(const float *__restrict__ w, T *__restrict__ out) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= 11 * 2 * 64 * 8) return;
+  const int e = idx & 7, lane = (idx >> 3) & 63, ct = (idx >> 9) & 1, u = idx >> 10;
+  const int co = ct * 32 + (lane & 31), v = 8 * (lane >> 5) + e;
+  out[idx] = from_f32<T>(v < 11 ? w[((long)co * 11 + u) * 11 + v] : 0.0f);
+}
+
+// conv_last weights: W [1][CIN][11][11] -> [CIN/16][11 u][11 v][16].
+template <typename T>
+__global__ void pack_last_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= CIN * 121) return;
+  const int c = idx & 15, v = (idx >> 4) % 11, u = (idx >> 4) / 11 % 11, cs = (idx >> 4) / 121;
+  out[idx] = from_f32<T>(w[((long)(cs * 16 + c) * 11 + u) * 11 + v]);
+}
+
+// per-pixel bias [C][H][W] -> [H][W][C]
+__global__ void pack_bias_hwc_kernel(const float *__restrict__ b, float *__restrict__ out, int C, int HW) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)C * HW) return;
+  const int c = (int)(idx % C), p = (int)(idx / C);
+  out[idx] = b[(long)c * HW + p];
+}
+
+template <typename TI, typename TO>
+__global__ void cast_kernel(const TI *__restrict__ in, TO *__restrict__ out, long n) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx < n) out[idx] = (TO)in[idx];
+}
+
+// y [B][M] fp32 -> [B][Mpad] T (zero-padded), the proxy GEMM's padded operand
+template <typename T>
+__global__ void pad_rows_kernel(const float *__restrict__ in, T *__restrict__ out, int B, int M, int Mpad) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)B * Mpad) return;
+  const int b = (int)(idx / Mpad), m = (int)(idx % Mpad);
+  out[idx] = from_f32<T>(m < M ? in[(long)b * M + m] : 0.0f);
+}
+
+hipError_t pack_fc(const float *w, void *out, int N, int M, int Mpad, int prec, hipStream_t s) {
+  const long n = (long)N * Mpad;
+  if (prec == 1) pack_fc_kernel<bf16><<<GRID1(n), 0, s>>>(w, (bf16 *)out, N, M, Mpad);
+  else pack_fc_kernel<float><<<GRID1(n), 0, s>>>(w, (float *)out, N, M, Mpad);
+  return hipGetLastError();
+}
+hipError_t pack_mid(const float *w, void *out, int CIN, int COUT, int flip, int prec, hipStream_t s) {
+  const long n = (long)CIN * COUT * 121;
+  if (prec == 1) pack_mid_kernel<bf16><<<GRID1(n), 0, s>>>(w, (bf16 *)out, CIN, COUT, flip);
+  else pack_mid_kernel<float><<<GRID1(n), 0, s>>>(w, (float *)out, CIN, COUT, flip);
+  return hipGetLastError();
+}
+hipError_t pack_first(const float *w, void *out, int prec, hipStream_t s) {
+  if (prec == 1) pack_first_kernel<bf16><<<GRID1(11 * 2 * 64 * 8), 0, s>>>(w, (bf16 *)out);
+  else pack_first_kernel<float><<<GRID1(11 * 2 * 64 * 8), 0, s>>>(w, (float *)out);
+  return hipGetLastError();
+}
+hipError_t pack_last(const float *w, void *out, int CIN, int prec, hipStream_t s) {
+  if (prec == 1) pack_last_kernel<bf16><<<GRID1(CIN * 121), 0, s>>>(w, (bf16 *)out, CIN);
+  else pack_last_kernel<float><<<GRID1(CIN * 121), 0, s>>>(w, (float *)out, CIN);
+  return hipGetLastError();
+}
+hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s) {
+  pack_bias_hwc_kernel<<<GRID1((long)C * HW), 0, s>>>(b, out, C, HW);
+  return hipGetLastError();
+}
+hipError_t cast_f32_f64(const float *in, double *out, long n, hipStream_t s) {
+  if (n > 0) cast_kernel<float, double><<<GRID1(n), 0, s>>>(in, out, n);
+  return hipGetLastError();
+}
+hipError_t cast_f64_f32(const double *in, float *out, long n, hipStream_t s) {
+  if (n > 0) cast_kernel<double, float><<<GRID1(n), 0, s>>>(in, out, n);
+  return hipGetLastError();
+}
+hipError_t pad_rows(const float *in, void *out, int B, int M, int Mpad, int prec, hipStream_t s) {
+  const long n = (long)B * Mpad;
+  if (n <= 0) return hipSuccess;
+  if (prec == 1) pad_rows_kernel<bf16><<<GRID1(n), 0, s>>>(in, (bf16 *)out, B, M, Mpad);
+  else pad_rows_kernel<float><<<GRID1(n), 0, s>>>(in, (float *)out, B, M, Mpad);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ loss and metrics
+// One block per image, FP64 reductions in a fixed order.
+// stats[b][4] = { ||xh-x||^2, PSNR (peak = max x), ||xh-x||/||x||, success (ratio <= 0.1) }
+// g (nullable) = scale * (xh - x), masked by (xh > 0) when relu_last.
+template <typename TX>
+__global__ __launch_bounds__(256) void image_stats_kernel(const TX *__restrict__ xh, const float *__restrict__ x,
+                                                          int N, double *__restrict__ stats,
+                                                          float *__restrict__ g, double *__restrict__ g64,
+                                                          double scale, int relu_last) {
+  __shared__ double s_sse[256], s_nx[256], s_mx[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double sse = 0.0, nx = 0.0, mx = -1e308;
+  for (int p = tid; p < N; p += 256) {
+    const double a = (double)xh[(long)b * N + p], t = (double)x[(long)b * N + p];
+    const double d = a - t;
+    sse += d * d;
+    nx += t * t;
+    mx = t > mx ? t : mx;
+    double gv = scale * d;
+    if (relu_last && !(a > 0.0)) gv = 0.0;
+    if (g) g[(long)b * N + p] = (float)gv;
+    if (g64) g64[(long)b * N + p] = gv;
+  }
+  s_sse[tid] = sse; s_nx[tid] = nx; s_mx[tid] = mx;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      s_sse[tid] += s_sse[tid + h];
+      s_nx[tid] += s_nx[tid + h];
+      s_mx[tid] = s_mx[tid] > s_mx[tid + h] ? s_mx[tid] : s_mx[tid + h];
+    }
+    __syncthreads();
+  }
+  if (tid == 0 && stats) {
+    const double e = s_sse[0], n2 = s_nx[0], peak = s_mx[0];
+    stats[b * 4 + 0] = e;
+    stats[b * 4 + 1] = 10.0 * log10(peak * peak / (e / N));
+    stats[b * 4 + 2] = n2 > 0.0 ? sqrt(e / n2) : sqrt(e);
+    stats[b * 4 + 3] = (e / n2 <= 0.1) ? 1.0 : 0.0;
+  }
+}
+
+// L = (1/B) sum_b sse_b, summed in image order
+__global__ void loss_sum_kernel(const double *__restrict__ stats, int B, double *__restrict__ loss) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int b = 0; b < B; ++b) s += stats[b * 4];
+    *loss = s / B;
+  }
+}
+
+hipError_t image_stats_f32(const float *xh, const float *x, int B, int N, double *stats, float *g,
+                           double scale, int relu_last, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  image_stats_kernel<float><<<B, 256, 0, s>>>(xh, x, N, stats, g, nullptr, scale, relu_last);
+  return hipGetLastError();
+}
+hipError_t image_stats_f64(const double *xh, const float *x, int B, int N, double *stats, double *g64,
+                           double scale, int relu_last, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  image_stats_kernel<double><<<B, 256, 0, s>>>(xh, x, N, stats, nullptr, g64, scale, relu_last);
+  return hipGetLastError();
+}
+hipError_t loss_sum(const double *stats, int B, double *loss, hipStream_t s) {
+  loss_sum_kernel<<<1, 64, 0, s>>>(stats, B, loss);
+  return hipGetLastError();
+}
+
+// g_out = g * (a > 0): gradient through the last layer's ReLU (relu_last)
+template <typename TA, typename TO>
+__global__ void relu_mask_kernel(const float *__restrict__ g, const TA *__restrict__ a, TO *__restrict__ out, long n) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx < n) out[idx] = (a == nullptr || a[idx] > (TA)0) ? (TO)g[idx] : (TO)0;
+}
+hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hipStream_t s) {
+  if (n > 0) relu_mask_kernel<float, float><<<GRID1(n), 0, s>>>(g, a, out, n);
+  return hipGetLastError();
+}
+hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, hipStream_t s) {
+  if (n > 0) relu_mask_kernel<double, double><<<GRID1(n), 0, s>>>(g, a, out, n);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------------------ Adam
+// theta -= lr * mhat / (sqrt(vhat) + eps), mhat = m / c1, vhat = v / c2
+template <typename TG>
+__global__ void adam_kernel(float *__restrict__ th, const TG *__restrict__ g, float *__restrict__ m,
+                            float *__restrict__ v, long n, float lr, float b1, float b2, float eps,
+                            float c1, float c2) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const float gi = (float)g[idx];
+  const float mi = b1 * m[idx] + (1.0f - b1) * gi;
+  const float vi = b2 * v[idx] + (1.0f - b2) * gi * gi;
+  m[idx] = mi;
+  v[idx] = vi;
+  th[idx] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+}
+hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float lr, float b1, float b2,
+                    float eps, float c1, float c2, hipStream_t s) {
+  if (n > 0) adam_kernel<float><<<GRID1(n), 0, s>>>(th, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+
+}  // namespace dsi

@@ -1,0 +1,182 @@
+"""GPU parity of the recovery path (measurement, proxy, Eq. (1) conv stack)
+against the FP64 oracle, through the C ABI.
+
+Tolerances (norm-wise relative error per image against the FP64 oracle on the
+same fp32 inputs): FP32 <= 1e-5, BF16 <= 2e-2, FP64 <= 1e-12.
+"""
+import numpy as np
+import pytest
+
+from cases import make_case, relerr_per_image
+
+pytestmark = pytest.mark.gpu
+
+TOL = {"f32": 1e-5, "bf16": 2e-2, "f64": 1e-12}
+
+
+@pytest.fixture(scope="module")
+def dsi():
+    import torch
+
+    import paper_1701_03891_amd as P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = P.Context(0)
+    yield P, ctx
+    ctx.close()
+
+
+def _recover(P, ctx, case, prec):
+    import torch
+    params = case.torch_params()
+    net = ctx.prepare(case.n1, case.n2, case.M, params, prec=prec, C=case.C, k=case.k,
+                      bias_per_pixel=case.bias_per_pixel, relu_last=case.relu_last)
+    y = torch.tensor(case.y, dtype=torch.float32, device="cuda")
+    xh = net.recover(y)
+    torch.cuda.synchronize()
+    out = xh.cpu().numpy().astype(np.float64).reshape(case.B, -1)
+    net.free()
+    return out
+
+
+# ---------------------------------------------------------------- Sec. 1
+@pytest.mark.parametrize("M,n1,n2,B", [(256, 32, 32, 8), (77, 40, 48, 3), (50, 13, 11, 5), (1024, 64, 64, 64)])
+def test_measure_parity(dsi, M, n1, n2, B):
+    import torch
+
+    import oracle
+    import synth
+    P, ctx = dsi
+    N = n1 * n2
+    phi = synth.make_phi(M, N, cfg_id=M + N)
+    x = synth.piecewise_smooth_images(B, n1, n2, cfg_id=M + N).reshape(B, N)
+    ref = oracle.measure(phi, x)
+    y = ctx.measure(torch.tensor(phi, dtype=torch.float32, device="cuda"),
+                    torch.tensor(x, dtype=torch.float32, device="cuda"))
+    got = y.cpu().numpy().astype(np.float64)
+    assert relerr_per_image(got, ref).max() <= 1e-5
+
+
+def test_measure_empty_batch_is_noop(dsi):
+    import torch
+    P, ctx = dsi
+    phi = torch.ones((4, 16), device="cuda")
+    x = torch.ones((0, 16), device="cuda")
+    y = ctx.measure(phi, x)
+    assert y.shape == (0, 4)
+
+
+# ---------------------------------------------------------------- Sec. 4
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_recover_c1_dct_sparse(dsi, prec):
+    """32x32 DCT-sparse signals (K = 40), M = 256, batch 8, He-init, ReLU after layers 1-2."""
+    P, ctx = dsi
+    case = make_case(32, 32, 256, 8, cfg_id=1, signal="dct", bias_std=0.0)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, prec)
+    err = relerr_per_image(got, ref)
+    print(f"C1 {prec}: max rel err {err.max():.3e}")
+    assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("bias_per_pixel", [True, False])
+def test_recover_ragged_tiles(dsi, prec, bias_per_pixel):
+    """40x48 images (ragged against 32-wide and 16/32-high tiles), M = 500 (padded K), batch 3."""
+    P, ctx = dsi
+    case = make_case(40, 48, 500, 3, cfg_id=2, bias_per_pixel=bias_per_pixel, bias_std=0.05)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, prec)
+    err = relerr_per_image(got, ref)
+    print(f"ragged {prec} bias_pp={bias_per_pixel}: max rel err {err.max():.3e}")
+    assert err.max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_recover_image_smaller_than_filter(dsi, prec):
+    """5x7 images, smaller than the 11x11 filters (taps reach the zero padding); M = 3; batch 2."""
+    P, ctx = dsi
+    case = make_case(5, 7, 3, 2, cfg_id=3, bias_std=0.1)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, prec)
+    assert relerr_per_image(got, ref).max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_recover_relu_last_and_m_above_n(dsi, prec):
+    """relu_last = 1 (ReLU in every layer, as Sec. 4 states) and M > N (allowed)."""
+    P, ctx = dsi
+    case = make_case(16, 16, 300, 2, cfg_id=4, relu_last=True, bias_std=0.05)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, prec)
+    assert relerr_per_image(got, ref).max() <= TOL[prec]
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_recover_c2_full_size_sampled(dsi, prec):
+    """64x64, M = 1024, batch 256 in the benchmark's launch configuration; the
+    oracle checks 4 sampled images (images are independent, pinned by P8)."""
+    P, ctx = dsi
+    case = make_case(64, 64, 1024, 256, cfg_id=5, bias_std=0.02)
+    got = _recover(P, ctx, case, prec)
+    idx = np.array([0, 97, 128, 255])
+    ref = case.oracle_forward(idx)
+    err = relerr_per_image(got[idx], ref)
+    print(f"C2 {prec}: sampled max rel err {err.max():.3e}")
+    assert err.max() <= TOL[prec]
+    assert np.all(np.isfinite(got))
+
+
+# ------------------------------------------------ any shape (direct kernels)
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_recover_generic_tiny_net(dsi, prec):
+    """16x16, M = 64, 1 -> 4 -> 2 -> 1 with 5x5 filters (the tiny net of the gradient checks)."""
+    P, ctx = dsi
+    case = make_case(16, 16, 64, 3, cfg_id=6, C=(1, 4, 2, 1), k=(5, 5, 5), bias_std=0.1)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, prec)
+    assert relerr_per_image(got, ref).max() <= TOL[prec]
+
+
+def test_recover_generic_deeper_net(dsi):
+    """A deeper, narrower stack (L = 5, mixed filter sizes): the direct-kernel path."""
+    P, ctx = dsi
+    case = make_case(20, 18, 90, 2, cfg_id=7, C=(1, 8, 6, 4, 3, 1), k=(3, 7, 5, 3, 9), bias_std=0.1)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, "f32")
+    assert relerr_per_image(got, ref).max() <= TOL["f32"]
+
+
+# -------------------------------------------------------------- error paths
+def test_error_paths(dsi):
+    import torch
+
+    from paper_1701_03891_amd import _lib
+    P, ctx = dsi
+    case = make_case(16, 16, 64, 2, cfg_id=8)
+    params = case.torch_params()
+    # BF16 on a non-paper architecture
+    tiny = make_case(16, 16, 64, 2, cfg_id=8, C=(1, 4, 2, 1), k=(5, 5, 5))
+    with pytest.raises(P.DsiError) as e:
+        ctx.prepare(16, 16, 64, tiny.torch_params(), prec="bf16", C=tiny.C, k=tiny.k)
+    assert e.value.status == _lib.DSI_E_DTYPE
+    # even filter size
+    with pytest.raises(P.DsiError) as e:
+        ctx.prepare(16, 16, 64, tiny.torch_params(), prec="f32", C=tiny.C, k=(5, 4, 5))
+    assert e.value.status == _lib.DSI_E_SHAPE
+    net = ctx.prepare(16, 16, 64, params, prec="bf16")
+    y = torch.tensor(case.y, dtype=torch.float32, device="cuda")
+    out = torch.full((2, 16, 16), 7.0, device="cuda")
+    # misaligned y: status DSI_E_ALIGN and the output untouched
+    buf = torch.zeros(2 * 64 + 1, device="cuda")
+    st = _lib.lib().dsi_recover(ctx.h, net.h, buf.data_ptr() + 4, out.data_ptr(), 2, None)
+    assert st == _lib.DSI_E_ALIGN
+    st = _lib.lib().dsi_recover(ctx.h, net.h, None, out.data_ptr(), 2, None)
+    assert st == _lib.DSI_E_NULL
+    st = _lib.lib().dsi_recover(ctx.h, net.h, y.data_ptr(), out.data_ptr(), -1, None)
+    assert st == _lib.DSI_E_SHAPE
+    torch.cuda.synchronize()
+    assert torch.all(out == 7.0)
+    # B = 0 is a no-op
+    assert _lib.lib().dsi_recover(ctx.h, net.h, None, None, 0, None) == _lib.DSI_OK
+    net.free()
