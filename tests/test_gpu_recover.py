@@ -2,7 +2,9 @@
 against the FP64 oracle, through the C ABI.
 
 Tolerances (norm-wise relative error per image against the FP64 oracle on the
-same fp32 inputs): FP32 <= 1e-5, BF16 <= 2e-2, FP64 <= 1e-12.
+same fp32 inputs): FP32 <= 1e-5, BF16 <= 2e-2.  The FP64 checking precision
+returns xhat through the same float32 interface, so its bound is the float32
+rounding of the output (2^-24 relative per element): 1e-7.
 """
 import numpy as np
 import pytest
@@ -11,7 +13,7 @@ from cases import make_case, relerr_per_image
 
 pytestmark = pytest.mark.gpu
 
-TOL = {"f32": 1e-5, "bf16": 2e-2, "f64": 1e-12}
+TOL = {"f32": 1e-5, "bf16": 2e-2, "f64": 1e-7}
 
 
 @pytest.fixture(scope="module")
