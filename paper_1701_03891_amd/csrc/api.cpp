@@ -239,7 +239,7 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
   }
   HIPCHK(dsi::pack_first(p->w[0], n->wp1, pr, s));
   HIPCHK(dsi::pack_mid(p->w[1], n->wp2, 64, 32, 0, pr, s));
-  HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, pr, s));
+  HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, pr, s));
   for (int l = 0; l < 3; ++l) {
     const int C = d.C[l + 1];
     if (d.bias_per_pixel && C > 1) HIPCHK(dsi::pack_bias_hwc(p->b[l], n->bp[l], C, HW, s));
@@ -303,24 +303,26 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     bf16 *xt = at<bf16>(base, L.xt), *a1 = at<bf16>(base, L.act[1]), *a2 = at<bf16>(base, L.act[2]);
     HIPCHK(dsi::gemm_nt_bf16_out_bf16(yk, ldy, (const bf16 *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
     clk.mark();
-    HIPCHK(dsi::conv_first<bf16>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, a1, B, H, W, s));
+    HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, bf16>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
+                                                               nullptr, a1, B, H, W, s)));
     clk.mark();
     HIPCHK((dsi::conv_mid<bf16, 64, 32, dsi::EPI_BIAS, bf16>(a1, (const bf16 *)n->wp2, n->bp[1],
                                                             d.bias_per_pixel, 1, nullptr, a2, B, H, W, s)));
     clk.mark();
-    HIPCHK(dsi::conv_last<bf16>(a2, (const bf16 *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
+    HIPCHK((dsi::conv_last<bf16, 32>)(a2, (const bf16 *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
                                 xout_last, B, H, W, s));
     clk.mark();
   } else {
     float *xt = at<float>(base, L.xt), *a1 = at<float>(base, L.act[1]), *a2 = at<float>(base, L.act[2]);
     HIPCHK(dsi::gemm_nt_f32(yk, ldy, (const float *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
     clk.mark();
-    HIPCHK(dsi::conv_first<float>(xt, (const float *)n->wp1, n->bp[0], d.bias_per_pixel, a1, B, H, W, s));
+    HIPCHK((dsi::conv_first<float, 64, dsi::EPI_BIAS, float, float>(xt, (const float *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
+                                                               nullptr, a1, B, H, W, s)));
     clk.mark();
     HIPCHK((dsi::conv_mid<float, 64, 32, dsi::EPI_BIAS, float>(a1, (const float *)n->wp2, n->bp[1],
                                                               d.bias_per_pixel, 1, nullptr, a2, B, H, W, s)));
     clk.mark();
-    HIPCHK(dsi::conv_last<float>(a2, (const float *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
+    HIPCHK((dsi::conv_last<float, 32>)(a2, (const float *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
                                  xout_last, B, H, W, s));
     clk.mark();
   }

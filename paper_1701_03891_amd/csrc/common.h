@@ -131,4 +131,19 @@ template <typename T> DSI_INLINE Frag8<T> frag_from(const float *x) {
   return f;
 }
 
+// keep elements [0, KEEP) of a fragment slice, zero the rest
+template <typename T, int KEEP> DSI_INLINE Frag8<T> frag_keep_first(Frag8<T> f) {
+  if constexpr (sizeof(T) == 2) {
+#pragma unroll
+    for (int e = KEEP; e < 8; ++e) f.v[e] = (bf16)0.0f;
+  } else {
+#pragma unroll
+    for (int e = KEEP; e < 8; ++e) {
+      if (e < 4) f.lo[e] = 0.0f;
+      else f.hi[e - 4] = 0.0f;
+    }
+  }
+  return f;
+}
+
 __host__ __device__ inline int ceil_div(int a, int b) { return (a + b - 1) / b; }

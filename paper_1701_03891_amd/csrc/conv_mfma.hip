@@ -162,27 +162,32 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
 }
 
 // =================================================================== conv_first
-// in  [B][H][W] (T), wp [11 u][COUT/32][64][8] (T): lane l holds
+// One input channel -> COUT channels.  in [B][H][W] (TI, converted to T while
+// staged), wp [11 u][COUT/32][64][8] (T): lane l holds
 //     W[co = ct*32 + l%32][0][u][v = 8*(l/32) + e] (0 for v >= 11)
-// out [B][COUT/16][H][W][16] (T)
-template <typename T, int COUT>
-__global__ __launch_bounds__(256) void conv_first_kernel(const T *__restrict__ in, const T *__restrict__ wp,
-                                                         const float *__restrict__ bias, int bias_pp,
-                                                         T *__restrict__ out, int H, int W, int tiles_w,
-                                                         int tiles_per_img) {
+// out [B][COUT/16][H][W][16] (TO).
+// The B operand of the k-step for filter row u is 8 consecutive pixels of one
+// LDS row, read with one unaligned 16-byte LDS load.
+// EPI_BIAS: out = ReLU?(acc + bias);  EPI_MASK: out = acc * (mask > 0).
+template <typename T, int COUT, int EPI, typename TI, typename TO>
+__global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ in, const T *__restrict__ wp,
+                                                         const float *__restrict__ bias, int bias_pp, int relu,
+                                                         const T *__restrict__ mask, TO *__restrict__ out,
+                                                         int H, int W, int tiles_w, int tiles_per_img) {
   constexpr int ROWS = 4, TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
+  constexpr int LWA = LW + 8;  // zero columns so the 8-wide reads of the last lanes stay in the tile
   constexpr int NCT = COUT / 32;
-  __shared__ T tile[LH * LW + 16];
+  __shared__ __attribute__((aligned(16))) T tile[LH * LWA];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
   const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  const T *src = in + (long)img * H * W;
-  for (int idx = tid; idx < LH * LW; idx += 256) {
-    const int row = idx / LW, col = idx - row * LW;
+  const TI *src = in + (long)img * H * W;
+  for (int idx = tid; idx < LH * LWA; idx += 256) {
+    const int row = idx / LWA, col = idx - row * LWA;
     const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-    tile[idx] = (gi >= 0 && gi < H && gj >= 0 && gj < W) ? src[(long)gi * W + gj] : from_f32<T>(0.0f);
+    const bool inside = col < LW && gi >= 0 && gi < H && gj >= 0 && gj < W;
+    tile[idx] = from_f32<T>(inside ? to_f32(src[(long)gi * W + gj]) : 0.0f);
   }
-  if (tid < 16) tile[LH * LW + tid] = from_f32<T>(0.0f);
   __syncthreads();
 
   Frag8<T> wf[KT][NCT];
@@ -201,11 +206,10 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const T *__restrict__ i
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
 #pragma unroll
     for (int u = 0; u < KT; ++u) {
-      const T *p = tile + (lr + u) * LW + px + 8 * h;
-      float xs[8];
-#pragma unroll
-      for (int e = 0; e < 8; ++e) xs[e] = (8 * h + e < KT) ? to_f32(p[e]) : 0.0f;
-      Frag8<T> xf = frag_from<T>(xs);
+      // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e (unaligned)
+      Frag8<T> xf;
+      __builtin_memcpy(&xf, tile + (lr + u) * LWA + px + 8 * h, sizeof(xf));
+      if (h) xf = frag_keep_first<T, 3>(xf);  // taps v >= 11 are padding: keep them finite-free
 #pragma unroll
       for (int c = 0; c < NCT; ++c) wf[u][c].mma(xf, acc[c]);
     }
@@ -216,85 +220,118 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const T *__restrict__ i
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int co0 = c * 32 + 8 * q + 4 * h;
-        float bv[4];
-        load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
+        const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
         float vals[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vals[e] = fmaxf(acc[c][4 * q + e] + bv[e], 0.0f);
-        const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
-        store4<T>(out + o, vals[0], vals[1], vals[2], vals[3]);
+        for (int e = 0; e < 4; ++e) vals[e] = acc[c][4 * q + e];
+        if constexpr (EPI == EPI_BIAS) {
+          float bv[4];
+          load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            vals[e] += bv[e];
+            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+          }
+        } else {
+          float mv[4];
+          load4f<T>(mask + o, mv);
+#pragma unroll
+          for (int e = 0; e < 4; ++e) vals[e] = mv[e] > 0.0f ? vals[e] : 0.0f;
+        }
+        store4<TO>(out + o, vals[0], vals[1], vals[2], vals[3]);
       }
   }
 }
 
 // ==================================================================== conv_last
-// in [B][CIN/16][H][W][16] (T), w [CIN/16][11 u][11 v][16] (T, plain), out [B][H][W] fp32.
-// A thread computes 2 horizontally adjacent pixels; 16 x 16 threads cover 16 x 32.
-template <typename T> DSI_INLINE float dot16(const T *x, const T *w);
-template <> DSI_INLINE float dot16<bf16>(const bf16 *x, const bf16 *w) {
-  typedef __bf16 bf16x2_t __attribute__((ext_vector_type(2)));
-  const bf16x2_t *xa = reinterpret_cast<const bf16x2_t *>(x);
-  const bf16x2_t *wa = reinterpret_cast<const bf16x2_t *>(w);
-  float s = 0.0f;
-#pragma unroll
-  for (int q = 0; q < 8; ++q) s = __builtin_amdgcn_fdot2_f32_bf16(xa[q], wa[q], s, false);
-  return s;
-}
-template <> DSI_INLINE float dot16<float>(const float *x, const float *w) {
-  float s = 0.0f;
-#pragma unroll
-  for (int q = 0; q < 16; ++q) s = fmaf(x[q], w[q], s);
-  return s;
-}
+// CIN channels -> one output channel, as a banded-Toeplitz GEMM on 16x16 MFMAs.
+// A wave owns 16 output rows x 16 output columns.  For horizontal tap v and
+// each of the 26 input rows r of its halo:
+//     D[j][i] += sum_c in[c][r][j + v - 5] * W[c][u = r - i][v]   (0 <= u <= 10)
+// with M = output column j, N = output row i, K = input channels; the weight
+// operand is the band of W for that (r, v), zero outside it.  Summing over
+// r and v covers every (u, v) exactly once; 11/26 of the MFMA work is useful.
+// in  [B][CIN/16][H][W][16] (T); wt [11 v][11 u][CIN] (T); out [B][H][W] fp32.
+// Each pass over LDS holds 64 bytes of channels per pixel (32 bf16 / 16 fp32),
+// as four 16-byte units; lane group g = l/16 reads unit g of its pixel.
+template <typename T> DSI_INLINE void mma16(const Frag8<T> &a, const Frag8<T> &b, f32x4 &acc);
 
 template <typename T, int CIN>
-__global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in, const T *__restrict__ w,
+__global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in, const T *__restrict__ wt,
                                                         const float *__restrict__ bias, int bias_pp, int relu,
                                                         float *__restrict__ out, int H, int W, int tiles_w,
                                                         int tiles_per_img) {
-  constexpr int TH = 16, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD, NCS = CIN / 16;
-  __shared__ __attribute__((aligned(16))) T tile[LH * LW * 16];
-  const int tid = threadIdx.x, ty = tid >> 4, tx = tid & 15;
+  constexpr int TH = 16, TW = 64, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
+  constexpr int EPU = 16 / (int)sizeof(T);   // elements per 16-byte unit
+  constexpr int CHL = 4 * EPU;               // channels per pass
+  constexpr int NPASS = CIN / CHL;
+  constexpr int UNIT_PLANE = LW * 16;        // bytes between unit planes of one LDS row
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * 4 * UNIT_PLANE];
+  __shared__ __attribute__((aligned(16))) T wl[KT * KT * CIN + 8];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
   const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  constexpr int PER16 = 16 / (int)sizeof(T) * 1;  // elements per 16-byte unit
-  float acc0 = 0.0f, acc1 = 0.0f;
-  for (int cs = 0; cs < NCS; ++cs) {
+  for (int idx = tid; idx < KT * KT * CIN; idx += 256) wl[idx] = wt[idx];
+  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  for (int pass = 0; pass < NPASS; ++pass) {
     __syncthreads();
-    const T *src = in + (long)(img * NCS + cs) * H * W * 16;
-    constexpr int UPP = 16 / PER16;  // 16-byte units per pixel
-    for (int idx = tid; idx < LH * LW * UPP; idx += 256) {
-      const int pix = idx / UPP, part = idx - pix * UPP;
+    // stage 16-byte units: unit q of pixel covers channels pass*CHL + q*EPU .. +EPU
+    for (int idx = tid; idx < LH * LW * 4; idx += 256) {
+      const int q = idx / (LH * LW), pix = idx - q * (LH * LW);
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+      const int c0 = pass * CHL + q * EPU;
       i32x4 val = {0, 0, 0, 0};
       if (gi >= 0 && gi < H && gj >= 0 && gj < W)
-        val = *reinterpret_cast<const i32x4 *>(src + ((long)gi * W + gj) * 16 + part * PER16);
-      *reinterpret_cast<i32x4 *>(tile + pix * 16 + part * PER16) = val;
+        val = *reinterpret_cast<const i32x4 *>(in + ((((long)img * (CIN / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
+      *reinterpret_cast<i32x4 *>(lds + (row * 4 + q) * UNIT_PLANE + col * 16) = val;
     }
     __syncthreads();
-    const T *wcs = w + (long)cs * KT * KT * 16;
-    for (int u = 0; u < KT; ++u) {
-      const T *lrow = tile + ((ty + u) * LW + 2 * tx) * 16;
+    for (int v = 0; v < KT; ++v) {
+      const unsigned char *arow = lds + g * UNIT_PLANE + (wave * 16 + n + v) * 16;
+      const T *wv = wl + v * KT * CIN + pass * CHL + g * EPU;
 #pragma unroll
-      for (int v = 0; v < KT; ++v) {
-        const T *wv = wcs + (u * KT + v) * 16;  // uniform across the block
-        acc0 += dot16<T>(lrow + v * 16, wv);
-        acc1 += dot16<T>(lrow + (v + 1) * 16, wv);
+      for (int r = 0; r < LH; ++r) {
+        Frag8<T> a, b;
+        if constexpr (sizeof(T) == 2) {
+          a.v = *reinterpret_cast<const bf16x8 *>(arow + r * 4 * UNIT_PLANE);
+        } else {
+          a.lo = *reinterpret_cast<const f32x4 *>(arow + r * 4 * UNIT_PLANE);
+        }
+        const int u = r - n;  // filter row that links input row r to output row n
+        const bool band = u >= 0 && u < KT;
+        const T *wp = wv + (band ? u : 0) * CIN;
+        if constexpr (sizeof(T) == 2) {
+          b.v = *reinterpret_cast<const bf16x8 *>(wp);
+          if (!band) b = frag_zero<T>();
+        } else {
+          b.lo = *reinterpret_cast<const f32x4 *>(wp);
+          if (!band) b.lo = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+        }
+        mma16<T>(a, b, acc);
       }
     }
   }
-  const int gi = bi0 + ty, gj = bj0 + 2 * tx;
+  // lane holds output row n, columns 4g .. 4g+3 of the wave's 16
+  const int gi = bi0 + n;
   if (gi >= H) return;
-  float *o = out + ((long)img * H + gi) * W;
-  if (gj < W) {
-    float v = acc0 + (bias_pp ? bias[(long)gi * W + gj] : bias[0]);
-    o[gj] = relu ? fmaxf(v, 0.0f) : v;
+  const int gj0 = bj0 + wave * 16 + 4 * g;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int gj = gj0 + e;
+    if (gj >= W) break;
+    float v = acc[e];
+    if (bias) v += bias_pp ? bias[(long)gi * W + gj] : bias[0];
+    out[((long)img * H + gi) * W + gj] = relu ? fmaxf(v, 0.0f) : v;
   }
-  if (gj + 1 < W) {
-    float v = acc1 + (bias_pp ? bias[(long)gi * W + gj + 1] : bias[0]);
-    o[gj + 1] = relu ? fmaxf(v, 0.0f) : v;
-  }
+}
+
+template <> DSI_INLINE void mma16<bf16>(const Frag8<bf16> &a, const Frag8<bf16> &b, f32x4 &acc) {
+  acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
+}
+template <> DSI_INLINE void mma16<float>(const Frag8<float> &a, const Frag8<float> &b, f32x4 &acc) {
+#pragma unroll
+  for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[e], b.lo[e], acc, 0, 0, 0);
 }
 
 // ==================================================================== launchers
@@ -303,13 +340,13 @@ static inline void tiles(int H, int W, int TH, int TW, int &tw, int &tpi) {
   tpi = tw * ((H + TH - 1) / TH);
 }
 
-template <typename T>
-hipError_t conv_first(const T *in, const T *wp, const float *bias, int bias_pp, T *out, int B, int H,
-                      int W, hipStream_t s) {
+template <typename T, int COUT, int EPI, typename TI, typename TO>
+hipError_t conv_first(const TI *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
+                      TO *out, int B, int H, int W, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   int tw, tpi;
   tiles(H, W, 16, 32, tw, tpi);
-  conv_first_kernel<T, 64><<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, out, H, W, tw, tpi);
+  conv_first_kernel<T, COUT, EPI, TI, TO><<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi);
   return hipGetLastError();
 }
 
@@ -325,21 +362,21 @@ hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, in
   return hipGetLastError();
 }
 
-template <typename T>
+template <typename T, int CIN>
 hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, int relu, float *out, int B,
                      int H, int W, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   int tw, tpi;
-  tiles(H, W, 16, 32, tw, tpi);
-  conv_last_kernel<T, 32><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
+  tiles(H, W, 16, 64, tw, tpi);
+  conv_last_kernel<T, CIN><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
   return hipGetLastError();
 }
 
-template hipError_t conv_first<bf16>(const bf16 *, const bf16 *, const float *, int, bf16 *, int, int, int, hipStream_t);
-template hipError_t conv_first<float>(const float *, const float *, const float *, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_first<bf16, 64, EPI_BIAS, bf16, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
+template hipError_t conv_first<float, 64, EPI_BIAS, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
 template hipError_t conv_mid<bf16, 64, 32, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
 template hipError_t conv_mid<float, 64, 32, EPI_BIAS, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
-template hipError_t conv_last<bf16>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
-template hipError_t conv_last<float>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_last<bf16, 32>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_last<float, 32>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
 
 }  // namespace dsi

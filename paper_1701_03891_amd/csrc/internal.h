@@ -37,13 +37,13 @@ template <typename TG, typename Acc, typename TD>
 hipError_t bias_grad(const TG *gz, ActView vg, int B, int per_pixel, TD *db, hipStream_t s);
 
 // conv_mfma.hip (the paper's 1 -> 64 -> 32 -> 1, 11 x 11 network)
-template <typename T>
-hipError_t conv_first(const T *in, const T *wp, const float *bias, int bias_pp, T *out, int B, int H,
-                      int W, hipStream_t s);
+template <typename T, int COUT, int EPI, typename TI, typename TO>
+hipError_t conv_first(const TI *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
+                      TO *out, int B, int H, int W, hipStream_t s);
 template <typename T, int CIN, int COUT, int EPI, typename TO>
 hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
                     TO *out, int B, int H, int W, hipStream_t s);
-template <typename T>
+template <typename T, int CIN>
 hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, int relu, float *out, int B,
                      int H, int W, hipStream_t s);
 
@@ -54,7 +54,7 @@ namespace dsi {
 hipError_t pack_fc(const float *w, void *out, int N, int M, int Mpad, int prec, hipStream_t s);
 hipError_t pack_mid(const float *w, void *out, int CIN, int COUT, int flip, int prec, hipStream_t s);
 hipError_t pack_first(const float *w, void *out, int prec, hipStream_t s);
-hipError_t pack_last(const float *w, void *out, int CIN, int prec, hipStream_t s);
+hipError_t pack_last(const float *w, void *out, int CIN, int flip, int prec, hipStream_t s);
 hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s);
 hipError_t cast_f32_f64(const float *in, double *out, long n, hipStream_t s);
 hipError_t cast_f64_f32(const double *in, float *out, long n, hipStream_t s);

@@ -49,13 +49,16 @@ __global__ void pack_first_kernel(const float *__restrict__ w, T *__restrict__ o
   out[idx] = from_f32<T>(v < 11 ? w[((long)co * 11 + u) * 11 + v] : 0.0f);
 }
 
-// conv_last weights: W [1][CIN][11][11] -> [CIN/16][11 u][11 v][16].
+// conv_last weights: W [1][CIN][11][11] -> [11 v][11 u][CIN].
+// flip = 1 packs the data-gradient operator of a (1 -> CIN) layer instead:
+// W'[0][c][u][v] = W[c][0][10-u][10-v].
 template <typename T>
-__global__ void pack_last_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN) {
+__global__ void pack_last_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN, int flip) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= CIN * 121) return;
-  const int c = idx & 15, v = (idx >> 4) % 11, u = (idx >> 4) / 11 % 11, cs = (idx >> 4) / 121;
-  out[idx] = from_f32<T>(w[((long)(cs * 16 + c) * 11 + u) * 11 + v]);
+  const int c = idx % CIN, u = (idx / CIN) % 11, v = idx / CIN / 11;
+  const float val = flip ? w[((long)c * 11 + (10 - u)) * 11 + (10 - v)] : w[((long)c * 11 + u) * 11 + v];
+  out[idx] = from_f32<T>(val);
 }
 
 // per-pixel bias [C][H][W] -> [H][W][C]
@@ -98,9 +101,9 @@ hipError_t pack_first(const float *w, void *out, int prec, hipStream_t s) {
   else pack_first_kernel<float><<<GRID1(11 * 2 * 64 * 8), 0, s>>>(w, (float *)out);
   return hipGetLastError();
 }
-hipError_t pack_last(const float *w, void *out, int CIN, int prec, hipStream_t s) {
-  if (prec == 1) pack_last_kernel<bf16><<<GRID1(CIN * 121), 0, s>>>(w, (bf16 *)out, CIN);
-  else pack_last_kernel<float><<<GRID1(CIN * 121), 0, s>>>(w, (float *)out, CIN);
+hipError_t pack_last(const float *w, void *out, int CIN, int flip, int prec, hipStream_t s) {
+  if (prec == 1) pack_last_kernel<bf16><<<GRID1(CIN * 121), 0, s>>>(w, (bf16 *)out, CIN, flip);
+  else pack_last_kernel<float><<<GRID1(CIN * 121), 0, s>>>(w, (float *)out, CIN, flip);
   return hipGetLastError();
 }
 hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s) {
