@@ -159,6 +159,11 @@ dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, f
 dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, const void *saved,
                         size_t saved_bytes, int B, const dsi_grads *grads, float *gy,
                         void *stream);
+/* Copy activation `layer` of the state dsi_forward_train left in `saved`
+ * (0 = the proxy x~, 1..L-1 = the hidden feature maps after ReLU, L = xhat),
+ * converted to FP32, into out [B][C_layer][n1][n2] (planar, device). */
+dsi_status dsi_saved_activation(dsi_ctx *ctx, const dsi_net *net, const void *saved,
+                                size_t saved_bytes, int B, int layer, float *out, void *stream);
 /* Loss L = (1/B) sum_b ||xhat_b - x_b||^2 (Sec. 4, accumulated in FP64) and
  * its gradient with respect to every parameter (into grads, overwriting) and,
  * if gy is not NULL, to y [B][M]: forward, dL/dxhat = (2/B)(xhat - x), backward.

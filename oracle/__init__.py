@@ -63,6 +63,7 @@ def lib():
             "orc_loss": (d, [P, P, i, i, P]),
             "orc_backward": (d, [P, P, P, P, P, P, i, P, P, P, P]),
             "orc_adam": (None, [P, P, P, P, l_, l_, d, d, d, d]),
+            "orc_backward_acts": (None, [P, P, P, P, P, P, i, P, P, P, P]),
             "orc_psnr": (d, [P, P, i]),
             "orc_relerr": (d, [P, P, i]),
             "orc_success": (i, [P, P, i, d]),
@@ -267,6 +268,25 @@ def backward(net: Net, wfc, w, b, y, x, want_gy=False, want_gwfc=False) -> Grads
                            _p(gy) if gy is not None else None,
                            _p(gwfc) if gwfc is not None else None)
     return Grads(L, gw, gb, gy, gwfc)
+
+
+def backward_acts(net: Net, wfc, w, y, acts, g_out, want_gy=False) -> Grads:
+    """Backpropagation (Sec. 4) from GIVEN activations: acts[b] = [a_0, ..., a_L]
+    (each [C_l][n1][n2]), g_out = dL/dxhat [B][N].  ReLU masks come from the
+    given post-activations, so a network whose forward pass ran elsewhere
+    (e.g. in reduced precision) can be differentiated exactly in FP64."""
+    wfc, y, g_out = _c(wfc), _c(y), _c(g_out)
+    ws = [_c(a) for a in w]
+    B = y.shape[0]
+    flat = np.ascontiguousarray(np.stack([np.concatenate([np.asarray(a, dtype=np.float64).ravel()
+                                                           for a in acts[b]]) for b in range(B)]))
+    gw = [np.empty_like(a) for a in ws]
+    gb = [np.empty(net.full_bias_shape(l) if net.bias_full else (net.C[l + 1],)) for l in range(net.L)]
+    gy = np.empty_like(y) if want_gy else None
+    cn = net._c()
+    lib().orc_backward_acts(ctypes.byref(cn), _p(wfc), _ptr_array(ws), _p(y), _p(flat), _p(g_out), B,
+                            _ptr_array(gw), _ptr_array(gb), _p(gy) if gy is not None else None, None)
+    return Grads(float("nan"), gw, gb, gy, None)
 
 
 def adam(theta, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -220,13 +220,46 @@ static void backward_one(const orc_net *net, const double *wfc, const double *co
   free(ga);
 }
 
+/* Sum of per-image gradient blocks in image order (deterministic). */
+static void sum_private(const orc_net *net, const double *priv, long np, long nfc, int B,
+                        double *const *gw, double *const *gb, double *gwfc) {
+  const int L = net->L;
+  for (int l = 0; l < L; ++l) {
+    memset(gw[l], 0, sizeof(double) * nparams_w(net, l));
+    memset(gb[l], 0, sizeof(double) * nparams_b(net, l));
+  }
+  if (gwfc) memset(gwfc, 0, sizeof(double) * nfc);
+  for (int bi = 0; bi < B; ++bi) {
+    const double *pg = priv + (long)bi * (np + nfc);
+    for (int l = 0; l < L; ++l) {
+      for (long q = 0; q < nparams_w(net, l); ++q) gw[l][q] += *pg++;
+      for (long q = 0; q < nparams_b(net, l); ++q) gb[l][q] += *pg++;
+    }
+    if (gwfc)
+      for (long q = 0; q < nfc; ++q) gwfc[q] += pg[q];
+  }
+}
+
+static long nparams_all(const orc_net *net) {
+  long np = 0;
+  for (int l = 0; l < net->L; ++l) np += nparams_w(net, l) + nparams_b(net, l);
+  return np;
+}
+
+static void split_private(const orc_net *net, double *pg, double **gwl, double **gbl, double **fc) {
+  for (int l = 0; l < net->L; ++l) {
+    gwl[l] = pg; pg += nparams_w(net, l);
+    gbl[l] = pg; pg += nparams_b(net, l);
+  }
+  *fc = pg;
+}
+
 double orc_backward(const orc_net *net, const double *wfc, const double *const *w,
                     const double *const *b, const double *y, const double *x, int B,
                     double *const *gw, double *const *gb, double *gy, double *gwfc) {
   const int N = net->n1 * net->n2, M = net->M, L = net->L;
   const long per = orc_acts_per_image(net);
-  long np = 0;
-  for (int l = 0; l < L; ++l) np += nparams_w(net, l) + nparams_b(net, l);
+  const long np = nparams_all(net);
   const long nfc = gwfc ? (long)N * M : 0;
   /* one private gradient block per image, summed afterwards in image order */
   double *priv = (double *)calloc((size_t)B * (np + nfc), sizeof(double));
@@ -245,36 +278,55 @@ double orc_backward(const orc_net *net, const double *wfc, const double *const *
       g[p] = 2.0 * d / B;     /* dL/dxhat with L = (1/B) sum_b ||xhat_b - x_b||^2 */
     }
     sse[bi] = s;
-    double *pg = priv + (long)bi * (np + nfc);
-    double *gwl[8], *gbl[8];
-    for (int l = 0; l < L; ++l) {
-      gwl[l] = pg; pg += nparams_w(net, l);
-      gbl[l] = pg; pg += nparams_b(net, l);
-    }
+    double *gwl[8], *gbl[8], *fc;
+    split_private(net, priv + (long)bi * (np + nfc), gwl, gbl, &fc);
     backward_one(net, wfc, w, y + (long)bi * M, act, g, gwl, gbl,
-                 gy ? gy + (long)bi * M : NULL, gwfc ? pg : NULL);
+                 gy ? gy + (long)bi * M : NULL, gwfc ? fc : NULL);
     free(g);
     free(act);
   }
-  for (int l = 0; l < L; ++l) {
-    memset(gw[l], 0, sizeof(double) * nparams_w(net, l));
-    memset(gb[l], 0, sizeof(double) * nparams_b(net, l));
-  }
-  if (gwfc) memset(gwfc, 0, sizeof(double) * nfc);
+  sum_private(net, priv, np, nfc, B, gw, gb, gwfc);
   double loss = 0.0;
-  for (int bi = 0; bi < B; ++bi) {
-    const double *pg = priv + (long)bi * (np + nfc);
-    for (int l = 0; l < L; ++l) {
-      for (long q = 0; q < nparams_w(net, l); ++q) gw[l][q] += *pg++;
-      for (long q = 0; q < nparams_b(net, l); ++q) gb[l][q] += *pg++;
-    }
-    if (gwfc)
-      for (long q = 0; q < nfc; ++q) gwfc[q] += pg[q];
-    loss += sse[bi];
-  }
+  for (int bi = 0; bi < B; ++bi) loss += sse[bi];
   free(priv);
   free(sse);
   return loss / B;
+}
+
+void orc_backward_acts(const orc_net *net, const double *wfc, const double *const *w,
+                       const double *y, const double *acts, const double *g_out, int B,
+                       double *const *gw, double *const *gb, double *gy, double *gwfc) {
+  const int N = net->n1 * net->n2, M = net->M, L = net->L;
+  const long per = orc_acts_per_image(net);
+  long given = 0;
+  for (int l = 0; l <= L; ++l) given += (long)net->C[l] * N;
+  const long np = nparams_all(net);
+  const long nfc = gwfc ? (long)N * M : 0;
+  double *priv = (double *)calloc((size_t)B * (np + nfc), sizeof(double));
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int bi = 0; bi < B; ++bi) {
+    /* activation block of backward_one: a_0..a_L as given; z_l = a_l inside the crop
+     * window (a > 0 exactly where z > 0 for a ReLU layer), 0 on the borders, which
+     * receive no gradient */
+    double *act = (double *)calloc((size_t)per, sizeof(double));
+    double *a[9], *z[8];
+    acts_layout(net, act, a, z);
+    memcpy(a[0], acts + (long)bi * given, sizeof(double) * given);
+    for (int l = 0; l < L; ++l) {
+      const int k = net->k[l], f2 = net->n2 + k - 1, r = (k - 1) / 2, f1 = net->n1 + k - 1;
+      for (int c = 0; c < net->C[l + 1]; ++c)
+        for (int i = 0; i < net->n1; ++i)
+          for (int j = 0; j < net->n2; ++j)
+            z[l][((long)c * f1 + i + r) * f2 + j + r] = a[l + 1][((long)c * net->n1 + i) * net->n2 + j];
+    }
+    double *gwl[8], *gbl[8], *fc;
+    split_private(net, priv + (long)bi * (np + nfc), gwl, gbl, &fc);
+    backward_one(net, wfc, w, y + (long)bi * M, act, g_out + (long)bi * N * net->C[L], gwl, gbl,
+                 gy ? gy + (long)bi * M : NULL, gwfc ? fc : NULL);
+    free(act);
+  }
+  sum_private(net, priv, np, nfc, B, gw, gb, gwfc);
+  free(priv);
 }
 
 /* ------------------------------------------------------ Adam (Kingma & Ba) */

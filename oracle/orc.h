@@ -79,6 +79,15 @@ double orc_backward(const orc_net *net, const double *wfc, const double *const *
                     const double *const *b, const double *y, const double *x, int B,
                     double *const *gw, double *const *gb, double *gy, double *gwfc);
 
+/* Backpropagation from given activations: acts holds, per image, a_0..a_L
+ * planar ([C_l][n1][n2] each, concatenated; a_0 the proxy, a_L the output)
+ * and g_out = dL/dxhat [B][N].  The ReLU masks are taken from the given
+ * post-activations.  Same gradients as orc_backward when the activations are
+ * the oracle's own forward ones. */
+void orc_backward_acts(const orc_net *net, const double *wfc, const double *const *w,
+                       const double *y, const double *acts, const double *g_out, int B,
+                       double *const *gw, double *const *gb, double *gy, double *gwfc);
+
 /* One Adam step (Kingma & Ba) on n parameters; t is the 1-based step count. */
 void orc_adam(double *theta, const double *g, double *m, double *v, long n, long t,
               double lr, double beta1, double beta2, double eps);

@@ -218,6 +218,15 @@ class Net:
                                _stream(self.ctx.device))
         return xhat, saved
 
+    def saved_activation(self, saved, B, layer):
+        """Activation `layer` (0 = proxy, L = xhat) of a forward_train state, as float32 [B][C][n1][n2]."""
+        torch = _torch()
+        C = self.desc.C[layer]
+        out = torch.empty((B, C, self.n1, self.n2), dtype=torch.float32, device=saved.device)
+        _lib.dsi_saved_activation(self.ctx.h, self.h, _ptr(saved), saved.numel(), B, layer, _ptr(out),
+                                  _stream(self.ctx.device))
+        return out
+
     def backward(self, gxhat, saved, params_like: NetParams, want_gy=False):
         torch = _torch()
         B = gxhat.shape[0]

@@ -27,7 +27,7 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_net_prepare", "dsi_net_update", "dsi_net_set_act_scales", "dsi_net_free",
            "dsi_net_info", "dsi_workspace_size", "dsi_reserve", "dsi_recover",
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
-           "dsi_set_stage_timing", "dsi_stage_times"]
+           "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation"]
 
 
 class DsiError(RuntimeError):
@@ -90,6 +90,7 @@ def lib() -> ctypes.CDLL:
                                 ctypes.c_float, P, P]),
         "dsi_metrics": (st, [P, P, P, i, i, P, P]),
         "dsi_set_stage_timing": (st, [P, i]),
+        "dsi_saved_activation": (st, [P, P, P, z, i, i, P, P]),
         "dsi_stage_times": (st, [P, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
@@ -195,3 +196,7 @@ def dsi_stage_times(ctx, nstages=4):
     n = ctypes.c_int()
     call("dsi_stage_times", ctx, arr, nstages, ctypes.byref(n))
     return list(arr), n.value
+
+
+def dsi_saved_activation(ctx, net, saved, saved_bytes, B, layer, out, stream):
+    call("dsi_saved_activation", ctx, net, saved, saved_bytes, B, layer, out, stream)

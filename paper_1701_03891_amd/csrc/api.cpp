@@ -108,6 +108,7 @@ struct dsi_net {
   float *bp[3] = {};                                     // fp32 biases, per-pixel ones as [H][W][C]
   float *w32[3] = {};                                    // OIHW fp32 copies (backward)
   float *b32[3] = {};                                    // fp32 biases in caller layout (backward)
+  void *wp3f = nullptr, *wp2f = nullptr, *wp1f = nullptr;  // packed data-gradient operators
   float act_scale[DSI_MAX_LAYERS + 1];
 };
 
@@ -196,6 +197,7 @@ void free_net_buffers(dsi_net *n) {
   void *t = n->wfcT; f(t); n->wfcT = nullptr;
   for (int l = 0; l < DSI_MAX_LAYERS; ++l) { f(n->w[l]); f(n->b[l]); }
   f(n->wp1); f(n->wp2); f(n->wp3);
+  f(n->wp3f); f(n->wp2f); f(n->wp1f);
   for (int l = 0; l < 3; ++l) {
     void *a = n->bp[l]; f(a); n->bp[l] = nullptr;
     void *c = n->w32[l]; f(c); n->w32[l] = nullptr;
@@ -237,9 +239,13 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
     }
     return DSI_OK;
   }
-  HIPCHK(dsi::pack_first(p->w[0], n->wp1, pr, s));
+  HIPCHK(dsi::pack_first(p->w[0], n->wp1, 64, 0, pr, s));
   HIPCHK(dsi::pack_mid(p->w[1], n->wp2, 64, 32, 0, pr, s));
   HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, pr, s));
+  // data-gradient operators: layer 3 (32 <- 1), layer 2 (64 <- 32), layer 1 (1 <- 64)
+  HIPCHK(dsi::pack_first(p->w[2], n->wp3f, 32, 1, pr, s));
+  HIPCHK(dsi::pack_mid(p->w[1], n->wp2f, 32, 64, 1, pr, s));
+  HIPCHK(dsi::pack_last(p->w[0], n->wp1f, 64, 1, pr, s));
   for (int l = 0; l < 3; ++l) {
     const int C = d.C[l + 1];
     if (d.bias_per_pixel && C > 1) HIPCHK(dsi::pack_bias_hwc(p->b[l], n->bp[l], C, HW, s));
@@ -332,6 +338,9 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
 }
 
 // --------------------------------------------------------------- backward
+template <typename T>
+dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const Layout &L, int B, const dsi_grads *g,
+                          float *gy, void *scratch, hipStream_t s);
 // gz_last: dL/dz of the last layer (already masked when relu_last), [B][N] in the
 // path's gradient precision (fp32, or fp64 for DSI_F64).  Scratch for the
 // gradients of the hidden layers comes after the saved state in ws2.
@@ -377,6 +386,10 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
     }
     return DSI_OK;
   }
+  if (n->path == PATH_PAPER) {
+    if (n->prec == DSI_BF16) return backward_paper<bf16>(n, (const float *)gz_last, sv, L, B, g, gy, scratch, s);
+    return backward_paper<float>(n, (const float *)gz_last, sv, L, B, g, gy, scratch, s);
+  }
   // fp32 gradients; activations read in the path's storage (planar fp32, or blocked bf16/fp32)
   const bool paper = n->path == PATH_PAPER;
   int cmax = 1;
@@ -414,6 +427,64 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
   return DSI_OK;
 }
 
+int wgrad_chunks(int B) { return std::max(1, std::min(B, 16)); }
+
+// Backward of the paper's network on the MFMA kernels.  gz3 = dL/dz3 fp32 [B][N].
+// Scratch: g2 (T, [B][2][N][16]), g1 (T, [B][4][N][16]), gxt fp32 [B][N], wgrad partials.
+template <typename T>
+dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const Layout &L, int B, const dsi_grads *g,
+                          float *gy, void *scratch, hipStream_t s) {
+  const dsi_net_desc &d = n->d;
+  const int N = n->N, H = d.n1, W = d.n2, M = d.M, bpp = d.bias_per_pixel;
+  constexpr bool bf = sizeof(T) == 2;
+  T *xt = at<T>(sv, L.xt), *a1 = at<T>(sv, L.act[1]), *a2 = at<T>(sv, L.act[2]);
+  size_t off = 0;
+  T *g2 = at<T>(scratch, off); off += rnd((size_t)B * 32 * N * sizeof(T));
+  T *g1 = at<T>(scratch, off); off += rnd((size_t)B * 64 * N * sizeof(T));
+  float *gxt = at<float>(scratch, off); off += rnd((size_t)B * N * 4);
+  float *partial = at<float>(scratch, off);
+  const int nch = wgrad_chunks(B);
+  const ActView v1{1, H, W, 0}, v32{32, H, W, 1}, v64{64, H, W, 1};
+  // layer 3: dW3, db3, then g2 = (a2 > 0) * dgrad(gz3)
+  if constexpr (bf) {
+    HIPCHK(dsi::conv_wgrad_thin<float>(dsi::THIN_OUT, (const bf16 *)a2, gz3, 32, partial, nch, g->w[2], B, H, W, s));
+  } else {
+    HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>(gz3, v1, (const float *)a2, v32, B, 11, g->w[2], s)));
+  }
+  HIPCHK((dsi::bias_grad<float, float, float>(gz3, v1, B, bpp, g->b[2], s)));
+  HIPCHK((dsi::conv_first<T, 32, dsi::EPI_MASK, float, T>(gz3, (const T *)n->wp3f, nullptr, 0, 0, a2, g2, B, H, W, s)));
+  // layer 2: dW2, db2, then g1 = (a1 > 0) * dgrad(g2)
+  if constexpr (bf) {
+    HIPCHK(dsi::conv_wgrad_mid((const bf16 *)g2, (const bf16 *)a1, 64, partial, nch, g->w[1], B, H, W, s));
+  } else {
+    HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>((const float *)g2, v32, (const float *)a1, v64, B, 11, g->w[1], s)));
+  }
+  HIPCHK((dsi::bias_grad<T, float, float>(g2, v32, B, bpp, g->b[1], s)));
+  HIPCHK((dsi::conv_mid<T, 32, 64, dsi::EPI_MASK, T>(g2, (const T *)n->wp2f, nullptr, 0, 0, a1, g1, B, H, W, s)));
+  // layer 1: dW1, db1
+  if constexpr (bf) {
+    HIPCHK(dsi::conv_wgrad_thin<bf16>(dsi::THIN_IN, (const bf16 *)g1, (const bf16 *)xt, 64, partial, nch, g->w[0], B, H, W, s));
+  } else {
+    HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>((const float *)g1, v64, (const float *)xt, v1, B, 11, g->w[0], s)));
+  }
+  HIPCHK((dsi::bias_grad<T, float, float>(g1, v64, B, bpp, g->b[0], s)));
+  if (gy) {
+    // dL/dx~ = dgrad of layer 1, then dy = g_xt W_fc
+    HIPCHK((dsi::conv_last<T, 64>(g1, (const T *)n->wp1f, nullptr, 0, 0, gxt, B, H, W, s)));
+    if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
+    HIPCHK(dsi::gemm_nt_f32(gxt, N, n->wfcT, N, gy, M, B, M, N, N % 16 == 0, s));
+  }
+  return DSI_OK;
+}
+
+size_t backward_paper_scratch(const dsi_net &n, int B) {
+  const size_t N = n.N, es = n.es;
+  const int nch = wgrad_chunks(B);
+  size_t part = std::max({dsi::conv_wgrad_mid_partial_floats(64, nch), dsi::conv_wgrad_thin_partial_floats(64, nch),
+                          dsi::conv_wgrad_thin_partial_floats(32, nch)});
+  return rnd(B * 32 * N * es) + rnd(B * 64 * N * es) + rnd(B * N * 4) + rnd(part * 4);
+}
+
 size_t backward_scratch_bytes(const dsi_net &n, int B) {
   int cmax = 1;
   for (int l = 0; l <= n.d.L; ++l) cmax = std::max(cmax, n.d.C[l]);
@@ -425,6 +496,7 @@ size_t backward_scratch_bytes(const dsi_net &n, int B) {
     wmax = std::max<size_t>(wmax, (size_t)n.d.M * n.N);
     b += rnd(wmax * 8) + rnd((size_t)B * n.d.M * 8);
   }
+  if (n.path == PATH_PAPER) b = std::max(b, backward_paper_scratch(n, B));
   b += rnd((size_t)B * n.N * es);   // gz of the last layer
   b += rnd((size_t)B * 4 * 8) + 256; // per-image stats + loss
   return b;
@@ -509,6 +581,9 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
     A(&n->wp1, (size_t)11 * 2 * 64 * 8 * n->es);
     A(&n->wp2, (size_t)64 * 32 * 121 * n->es);
     A(&n->wp3, (size_t)32 * 121 * n->es);
+    A(&n->wp3f, (size_t)11 * 1 * 64 * 8 * n->es);
+    A(&n->wp2f, (size_t)32 * 64 * 121 * n->es);
+    A(&n->wp1f, (size_t)64 * 121 * n->es);
     for (int l = 0; l < 3; ++l) {
       A((void **)&n->bp[l], bcount(d, l) * 4);
       A((void **)&n->w32[l], wcount(d, l) * 4);
@@ -697,6 +772,26 @@ dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls) {
   }
   ctx->ev.clear();
   *calls = n;
+  return DSI_OK;
+}
+
+dsi_status dsi_saved_activation(dsi_ctx *ctx, const dsi_net *net, const void *saved, size_t saved_bytes, int B,
+                                int layer, float *out, void *stream) {
+  if (!ctx || !net || !saved || !out) return fail(DSI_E_NULL, "ctx, net, saved and out must be non-NULL");
+  const dsi_net_desc &d = net->d;
+  if (B < 1 || layer < 0 || layer > d.L) return fail(DSI_E_SHAPE, "B = %d, layer = %d", B, layer);
+  const Layout L = layout(*net, B, 1);
+  if (saved_bytes < L.end) return fail(DSI_E_SHAPE, "saved buffer has %zu bytes, needs %zu", saved_bytes, L.end);
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  void *sv = const_cast<void *>(saved);
+  const int C = d.C[layer];
+  const size_t off = layer == 0 ? L.xt : L.act[layer];
+  ActView v{C, d.n1, d.n2, (net->path == PATH_PAPER && C % 16 == 0) ? 1 : 0};
+  const bool out_layer = layer == d.L;
+  if (net->prec == DSI_F64) HIPCHK(dsi::unpack_act(at<double>(sv, off), v, out, B, s));
+  else if (out_layer || net->prec == DSI_F32) HIPCHK(dsi::unpack_act(at<float>(sv, off), v, out, B, s));
+  else HIPCHK(dsi::unpack_act(at<bf16>(sv, off), v, out, B, s));
   return DSI_OK;
 }
 

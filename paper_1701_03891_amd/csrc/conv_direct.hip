@@ -13,10 +13,6 @@
 
 namespace dsi {
 
-DSI_INLINE long act_idx(const ActView &v, int b, int c, int i, int j) {
-  return v.blocked ? ((((long)b * (v.C >> 4) + (c >> 4)) * v.H + i) * v.W + j) * 16 + (c & 15)
-                   : (((long)b * v.C + c) * v.H + i) * v.W + j;
-}
 
 template <typename Acc, typename T> DSI_INLINE Acc to_acc(T v) {
   if constexpr (sizeof(Acc) == 8 && sizeof(T) == 8) return v;
@@ -191,6 +187,7 @@ template hipError_t conv_wgrad_direct<float, float, float, float>(const float *,
 template hipError_t conv_wgrad_direct<double, double, double, double>(const double *, ActView, const double *, ActView, int, int, double *, hipStream_t);
 template hipError_t conv_wgrad_direct<float, bf16, float, float>(const float *, ActView, const bf16 *, ActView, int, int, float *, hipStream_t);
 
+template hipError_t bias_grad<bf16, float, float>(const bf16 *, ActView, int, int, float *, hipStream_t);
 template hipError_t bias_grad<float, float, float>(const float *, ActView, int, int, float *, hipStream_t);
 template hipError_t bias_grad<double, double, double>(const double *, ActView, int, int, double *, hipStream_t);
 

@@ -376,6 +376,12 @@ template hipError_t conv_first<bf16, 64, EPI_BIAS, bf16, bf16>(const bf16 *, con
 template hipError_t conv_first<float, 64, EPI_BIAS, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
 template hipError_t conv_mid<bf16, 64, 32, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
 template hipError_t conv_mid<float, 64, 32, EPI_BIAS, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
+template hipError_t conv_first<bf16, 32, EPI_MASK, float, bf16>(const float *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
+template hipError_t conv_first<float, 32, EPI_MASK, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
+template hipError_t conv_mid<bf16, 32, 64, EPI_MASK, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
+template hipError_t conv_mid<float, 32, 64, EPI_MASK, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
+template hipError_t conv_last<bf16, 64>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_last<float, 64>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
 template hipError_t conv_last<bf16, 32>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
 template hipError_t conv_last<float, 32>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
 

@@ -13,6 +13,11 @@ struct ActView {
 
 enum { EPI_BIAS = 0, EPI_MASK = 1 };
 
+__host__ __device__ inline long act_idx(const ActView &v, int b, int c, int i, int j) {
+  return v.blocked ? ((((long)b * (v.C >> 4) + (c >> 4)) * v.H + i) * v.W + j) * 16 + (c & 15)
+                   : (((long)b * v.C + c) * v.H + i) * v.W + j;
+}
+
 // gemm.hip: C[b][o] = sum_k X[b][k] W[o][k]
 hipError_t gemm_nt_f32(const float *X, long ldx, const float *W, long ldw, float *C, long ldc,
                        int Bn, int O, int K, bool vec, hipStream_t s);
@@ -53,7 +58,7 @@ namespace dsi {
 // misc.hip; prec: 0 = fp32, 1 = bf16
 hipError_t pack_fc(const float *w, void *out, int N, int M, int Mpad, int prec, hipStream_t s);
 hipError_t pack_mid(const float *w, void *out, int CIN, int COUT, int flip, int prec, hipStream_t s);
-hipError_t pack_first(const float *w, void *out, int prec, hipStream_t s);
+hipError_t pack_first(const float *w, void *out, int COUT, int flip, int prec, hipStream_t s);
 hipError_t pack_last(const float *w, void *out, int CIN, int flip, int prec, hipStream_t s);
 hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s);
 hipError_t cast_f32_f64(const float *in, double *out, long n, hipStream_t s);
@@ -64,8 +69,22 @@ hipError_t image_stats_f32(const float *xh, const float *x, int B, int N, double
 hipError_t image_stats_f64(const double *xh, const float *x, int B, int N, double *stats, double *g64,
                            double scale, int relu_last, hipStream_t s);
 hipError_t loss_sum(const double *stats, int B, double *loss, hipStream_t s);
+template <typename TI>
+hipError_t unpack_act(const TI *in, ActView vi, float *out, int B, hipStream_t s);
 hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hipStream_t s);
 hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, hipStream_t s);
 hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
+}  // namespace dsi
+
+namespace dsi {
+// conv_bwd.hip: MFMA weight gradients (bf16 operands, fp32 partials reduced in a fixed order)
+enum { THIN_OUT = 0, THIN_IN = 1 };
+size_t conv_wgrad_mid_partial_floats(int CIN, int nchunk);
+hipError_t conv_wgrad_mid(const __bf16 *g, const __bf16 *a, int CIN, float *partial, int nchunk, float *dw, int B,
+                          int H, int W, hipStream_t s);
+size_t conv_wgrad_thin_partial_floats(int CW, int nchunk);
+template <typename TT>
+hipError_t conv_wgrad_thin(int mode, const __bf16 *wide, const TT *thin, int CW, float *partial, int nchunk, float *dw,
+                           int B, int H, int W, hipStream_t s);
 }  // namespace dsi

@@ -39,14 +39,19 @@ __global__ void pack_mid_kernel(const float *__restrict__ w, T *__restrict__ out
   out[idx] = from_f32<T>(val);
 }
 
-// conv_first weights: W [64][1][11][11] -> [11 u][2 ct][64][8], taps v = 8*(lane/32) + e.
+// conv_first weights: W [COUT][1][11][11] -> [11 u][COUT/32][64][8], taps v = 8*(lane/32) + e.
+// flip = 1 packs the data-gradient operator of a (COUT -> 1) layer instead, whose
+// weights [1][COUT][11][11] have the same linear order: W'[c][0][u][v] = W[0][c][10-u][10-v].
 template <typename T>
-__global__ void pack_first_kernel(const float *__restrict__ w, T *__restrict__ out) {
+__global__ void pack_first_kernel(const float *__restrict__ w, T *__restrict__ out, int COUT, int flip) {
+  const int nct = COUT / 32;
   const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= 11 * 2 * 64 * 8) return;
-  const int e = idx & 7, lane = (idx >> 3) & 63, ct = (idx >> 9) & 1, u = idx >> 10;
+  if (idx >= 11 * nct * 64 * 8) return;
+  const int e = idx & 7, lane = (idx >> 3) & 63, ct = (idx >> 9) % nct, u = (idx >> 9) / nct;
   const int co = ct * 32 + (lane & 31), v = 8 * (lane >> 5) + e;
-  out[idx] = from_f32<T>(v < 11 ? w[((long)co * 11 + u) * 11 + v] : 0.0f);
+  float val = 0.0f;
+  if (v < 11) val = flip ? w[((long)co * 11 + (10 - u)) * 11 + (10 - v)] : w[((long)co * 11 + u) * 11 + v];
+  out[idx] = from_f32<T>(val);
 }
 
 // conv_last weights: W [1][CIN][11][11] -> [11 v][11 u][CIN].
@@ -96,9 +101,10 @@ hipError_t pack_mid(const float *w, void *out, int CIN, int COUT, int flip, int 
   else pack_mid_kernel<float><<<GRID1(n), 0, s>>>(w, (float *)out, CIN, COUT, flip);
   return hipGetLastError();
 }
-hipError_t pack_first(const float *w, void *out, int prec, hipStream_t s) {
-  if (prec == 1) pack_first_kernel<bf16><<<GRID1(11 * 2 * 64 * 8), 0, s>>>(w, (bf16 *)out);
-  else pack_first_kernel<float><<<GRID1(11 * 2 * 64 * 8), 0, s>>>(w, (float *)out);
+hipError_t pack_first(const float *w, void *out, int COUT, int flip, int prec, hipStream_t s) {
+  const int n = 11 * (COUT / 32) * 64 * 8;
+  if (prec == 1) pack_first_kernel<bf16><<<GRID1(n), 0, s>>>(w, (bf16 *)out, COUT, flip);
+  else pack_first_kernel<float><<<GRID1(n), 0, s>>>(w, (float *)out, COUT, flip);
   return hipGetLastError();
 }
 hipError_t pack_last(const float *w, void *out, int CIN, int flip, int prec, hipStream_t s) {
@@ -208,6 +214,26 @@ hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, h
   if (n > 0) relu_mask_kernel<double, double><<<GRID1(n), 0, s>>>(g, a, out, n);
   return hipGetLastError();
 }
+
+// saved activation -> planar fp32 [B][C][H][W]
+template <typename TI>
+__global__ void unpack_act_kernel(const TI *__restrict__ in, ActView vi, float *__restrict__ out, int B) {
+  const long n = (long)B * vi.C * vi.H * vi.W;
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= n) return;
+  const int j = (int)(idx % vi.W), i = (int)(idx / vi.W % vi.H), c = (int)(idx / ((long)vi.W * vi.H) % vi.C);
+  const int b = (int)(idx / ((long)vi.W * vi.H * vi.C));
+  out[idx] = to_f32(in[act_idx(vi, b, c, i, j)]);
+}
+template <typename TI>
+hipError_t unpack_act(const TI *in, ActView vi, float *out, int B, hipStream_t s) {
+  const long n = (long)B * vi.C * vi.H * vi.W;
+  if (n > 0) unpack_act_kernel<TI><<<GRID1(n), 0, s>>>(in, vi, out, B);
+  return hipGetLastError();
+}
+template hipError_t unpack_act<float>(const float *, ActView, float *, int, hipStream_t);
+template hipError_t unpack_act<double>(const double *, ActView, float *, int, hipStream_t);
+template hipError_t unpack_act<bf16>(const bf16 *, ActView, float *, int, hipStream_t);
 
 // ------------------------------------------------------------------ Adam
 // theta -= lr * mhat / (sqrt(vhat) + eps), mhat = m / c1, vhat = v / c2

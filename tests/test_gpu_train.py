@@ -1,0 +1,313 @@
+"""GPU parity of backpropagation and training (Sec. 4: L(Omega) minimised by
+backprop) against the FP64 oracle, through the C ABI.
+
+Gradient tolerances (norm-wise relative error per tensor): FP32 <= 1e-5 and
+the FP64 checking path <= 1e-6 (its gradients come back as float32) against
+the oracle's FP64 gradients for the same fp32 inputs.
+
+BF16: the gradient is a discontinuous function of the forward activations
+(ReLU kinks), and a BF16 forward pass moves the active set of the few units
+whose pre-activation lies within rounding of zero.  So the BF16 backward
+kernels are held to 2e-2 per tensor against the oracle's FP64
+backpropagation evaluated on the SAME forward state (the GPU's own saved
+activations, unpacked through dsi_saved_activation), and the end-to-end
+BF16-vs-FP64 gradient error is reported with a looser bound.
+"""
+import numpy as np
+import pytest
+
+from cases import make_case
+
+pytestmark = pytest.mark.gpu
+
+GTOL = {"f32": 1e-5, "bf16": 2e-2, "f64": 1e-6}
+
+
+@pytest.fixture(scope="module")
+def dsi():
+    import torch
+
+    import paper_1701_03891_amd as P
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    ctx = P.Context(0)
+    yield P, ctx
+    ctx.close()
+
+
+def _t(a):
+    import torch
+    return torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda")
+
+
+def _rel(a, ref):
+    a = np.asarray(a, dtype=np.float64).ravel()
+    ref = np.asarray(ref, dtype=np.float64).ravel()
+    return np.linalg.norm(a - ref) / max(np.linalg.norm(ref), 1e-300)
+
+
+def _gpu_grads(ctx, case, prec, want_gy=False):
+    import torch
+    params = case.torch_params()
+    net = ctx.prepare(case.n1, case.n2, case.M, params, prec=prec, C=case.C, k=case.k,
+                      bias_per_pixel=case.bias_per_pixel, relu_last=case.relu_last)
+    loss, g, gy = net.loss_grad(_t(case.y), _t(case.x), params, want_gy=want_gy)
+    torch.cuda.synchronize()
+    out = (loss.item(), [w.cpu().numpy() for w in g.w], [b.cpu().numpy() for b in g.b],
+           gy.cpu().numpy() if gy is not None else None)
+    net.free()
+    return out
+
+
+def _oracle_grads(case, idx=None, want_gy=False):
+    import oracle
+    y = case.y if idx is None else case.y[idx]
+    x = case.x if idx is None else case.x[idx]
+    G = oracle.backward(case.oracle_net(), case.phi.T, case.w, case.oracle_bias(), y, x, want_gy=want_gy)
+    gb = [oracle.crop_full(G.b[l], case.k[l]) if case.bias_per_pixel else G.b[l] for l in range(len(case.k))]
+    return G.loss, G.w, gb, G.y
+
+
+def _check(gpu, ref, tol, label):
+    lg, wg, bg, yg = gpu
+    lr, wr, br, yr = ref
+    errs = {"loss": abs(lg - lr) / abs(lr)}
+    for l in range(len(wr)):
+        errs[f"w{l}"] = _rel(wg[l], wr[l])
+        errs[f"b{l}"] = _rel(bg[l], br[l])
+    if yr is not None:
+        errs["y"] = _rel(yg, yr)
+    print(label, " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= tol}
+    assert not bad, (label, bad)
+
+
+# end-to-end BF16 vs FP64 bounds (mask flips included); weights / per-pixel tensors
+E2E_BF16 = {"loss": 2e-2, "w": 6e-2, "b": 1.2e-1, "y": 1e-1}
+
+
+def _gpu_grads_same_state(ctx, case, want_gy=False):
+    """BF16 GPU gradients and the oracle's FP64 backpropagation on the GPU's forward state."""
+    import torch
+
+    import oracle
+    params = case.torch_params()
+    net = ctx.prepare(case.n1, case.n2, case.M, params, prec="bf16", C=case.C, k=case.k,
+                      bias_per_pixel=case.bias_per_pixel, relu_last=case.relu_last)
+    y, B = _t(case.y), case.B
+    xh, saved = net.forward_train(y)
+    acts = [net.saved_activation(saved, B, l).cpu().numpy().astype(np.float64) for l in range(4)]
+    g_out = (2.0 / B) * (xh.reshape(B, -1).cpu().numpy().astype(np.float64) - case.x)
+    g, gy = net.backward(_t(g_out).reshape(B, case.n1, case.n2), saved, params, want_gy=want_gy)
+    torch.cuda.synchronize()
+    gpu = (float("nan"), [w.cpu().numpy() for w in g.w], [b.cpu().numpy() for b in g.b],
+           gy.cpu().numpy() if gy is not None else None)
+    H = oracle.backward_acts(case.oracle_net(), case.phi.T, case.w, case.y,
+                             [[acts[l][b] for l in range(4)] for b in range(B)], g_out, want_gy=want_gy)
+    gb = [oracle.crop_full(H.b[l], 11) if case.bias_per_pixel else H.b[l] for l in range(3)]
+    net.free()
+    return gpu, (float("nan"), H.w, gb, H.y)
+
+
+def _check_e2e_bf16(gpu, ref, label):
+    lg, wg, bg, yg = gpu
+    lr, wr, br, yr = ref
+    errs = {"loss": abs(lg - lr) / abs(lr)}
+    for l in range(len(wr)):
+        errs[f"w{l}"] = _rel(wg[l], wr[l])
+        errs[f"b{l}"] = _rel(bg[l], br[l])
+    if yr is not None:
+        errs["y"] = _rel(yg, yr)
+    print(label, "end-to-end vs FP64:", " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= E2E_BF16[k[0] if k != "loss" else "loss"]}
+    assert not bad, (label, bad)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+@pytest.mark.parametrize("bias_per_pixel", [True, False])
+def test_loss_grad_paper_net_ragged(dsi, prec, bias_per_pixel):
+    """40x48 images (ragged against 8-row strips, 64-column passes, 16-row tiles), M = 500, batch 3."""
+    P, ctx = dsi
+    case = make_case(40, 48, 500, 3, cfg_id=21, bias_per_pixel=bias_per_pixel, bias_std=0.05)
+    label = f"{prec} bias_pp={bias_per_pixel}"
+    if prec == "bf16":
+        gpu, ref = _gpu_grads_same_state(ctx, case, want_gy=True)
+        _check_same_state(gpu, ref, label)
+        _check_e2e_bf16(_gpu_grads(ctx, case, "bf16", want_gy=True), _oracle_grads(case, want_gy=True), label)
+    else:
+        _check(_gpu_grads(ctx, case, prec, want_gy=True), _oracle_grads(case, want_gy=True), GTOL[prec], label)
+
+
+def _check_same_state(gpu, ref, label):
+    _, wg, bg, yg = gpu
+    _, wr, br, yr = ref
+    errs = {}
+    for l in range(len(wr)):
+        errs[f"w{l}"] = _rel(wg[l], wr[l])
+        errs[f"b{l}"] = _rel(bg[l], br[l])
+    if yr is not None:
+        errs["y"] = _rel(yg, yr)
+    print(label, "same forward state:", " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= GTOL["bf16"]}
+    assert not bad, (label, bad)
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_loss_grad_relu_last_and_wide_image(dsi, prec):
+    """relu_last = 1, 20 x 80 images (two 64-column passes, ragged), M = 333, batch 2."""
+    P, ctx = dsi
+    case = make_case(20, 80, 333, 2, cfg_id=22, relu_last=True, bias_std=0.1)
+    if prec == "bf16":
+        gpu, ref = _gpu_grads_same_state(ctx, case, want_gy=True)
+        _check_same_state(gpu, ref, "bf16 relu_last")
+        _check_e2e_bf16(_gpu_grads(ctx, case, "bf16"), _oracle_grads(case), "bf16 relu_last")
+    else:
+        _check(_gpu_grads(ctx, case, prec), _oracle_grads(case), GTOL[prec], f"{prec} relu_last")
+
+
+@pytest.mark.parametrize("prec", ["f32", "f64"])
+def test_loss_grad_generic_tiny_net(dsi, prec):
+    """The tiny net (16x16, M = 64, 1->4->2->1, 5x5) on the direct kernels."""
+    P, ctx = dsi
+    case = make_case(16, 16, 64, 3, cfg_id=23, C=(1, 4, 2, 1), k=(5, 5, 5), bias_std=0.1)
+    _check(_gpu_grads(ctx, case, prec, want_gy=True), _oracle_grads(case, want_gy=True), GTOL[prec], prec)
+
+
+def test_finite_differences_fp64_on_gpu(dsi):
+    """FP64 central differences of the GPU's FP64 loss against the GPU's FP64 gradients (tiny net)."""
+    import torch
+    P, ctx = dsi
+    case = make_case(16, 16, 64, 3, cfg_id=24, C=(1, 4, 2, 1), k=(5, 5, 5), bias_std=0.1)
+    params = case.torch_params()
+    net = ctx.prepare(16, 16, 64, params, prec="f64", C=case.C, k=case.k)
+    y, x = _t(case.y), _t(case.x)
+    _, g, _ = net.loss_grad(y, x, params)
+    rng = np.random.default_rng(5)
+    checked = 0
+    for l in range(3):
+        for kind, arr, garr in (("w", params.w[l], g.w[l]), ("b", params.b[l], g.b[l])):
+            flat = arr.view(-1)
+            gflat = garr.view(-1).cpu().numpy().astype(np.float64)
+            for _ in range(5):
+                q = int(rng.integers(0, flat.numel()))
+                th = float(flat[q].item())
+                h = 2.0 ** -14 * max(1.0, abs(th))
+                vals = []
+                for sgn in (1, -1):
+                    flat[q] = th + sgn * h
+                    net.update(params)
+                    lv, _, _ = net.loss_grad(y, x, params)
+                    vals.append(lv.item())
+                flat[q] = th
+                tp, tm = np.float32(th + h), np.float32(th - h)
+                num = (vals[0] - vals[1]) / (float(tp) - float(tm))
+                scale = max(abs(gflat).max(), 1e-12)
+                assert abs(num - gflat[q]) <= 1e-5 * max(abs(gflat[q]), 1e-3 * scale), (kind, l, q, num, gflat[q])
+                checked += 1
+    net.update(params)
+    assert checked == 30
+    net.free()
+
+
+def test_full_size_batch_gradient_is_sum_of_subbatches(dsi):
+    """64x64, M = 1024, batch 128 (the training configuration): L = (1/B) sum, so the
+    batch gradient equals the mean of the gradients of 32 sub-batches of 4."""
+    import torch
+    P, ctx = dsi
+    case = make_case(64, 64, 1024, 128, cfg_id=25, bias_std=0.02)
+    params = case.torch_params()
+    net = ctx.prepare(64, 64, 1024, params, prec="bf16")
+    y, x = _t(case.y), _t(case.x)
+    loss, g, _ = net.loss_grad(y, x, params)
+    acc_w = [torch.zeros_like(w) for w in g.w]
+    acc_b = [torch.zeros_like(b) for b in g.b]
+    tot = 0.0
+    for s in range(0, 128, 4):
+        ls, gs, _ = net.loss_grad(y[s:s + 4].contiguous(), x[s:s + 4].contiguous(), params)
+        for l in range(3):
+            acc_w[l] += gs.w[l] / 32
+            acc_b[l] += gs.b[l] / 32
+        tot += ls.item() / 32
+    assert abs(loss.item() - tot) <= 1e-6 * abs(tot)
+    for l in range(3):
+        assert _rel(acc_w[l].cpu().numpy(), g.w[l].cpu().numpy()) <= 1e-4
+        assert _rel(acc_b[l].cpu().numpy(), g.b[l].cpu().numpy()) <= 1e-4
+    # and the first sub-batch against the oracle at full image size
+    case2 = make_case(64, 64, 1024, 128, cfg_id=25, bias_std=0.02)
+    ref = _oracle_grads(case2, idx=np.arange(2))
+    y2, x2 = y[:2].contiguous(), x[:2].contiguous()
+    l2, g2, _ = net.loss_grad(y2, x2, params)
+    _check_e2e_bf16((l2.item(), [w.cpu().numpy() for w in g2.w], [b.cpu().numpy() for b in g2.b], None), ref,
+                    "64x64 bf16 sub-batch")
+    net.free()
+
+
+def test_backward_is_deterministic_and_matches_forward_train(dsi):
+    import torch
+    P, ctx = dsi
+    case = make_case(32, 32, 256, 8, cfg_id=26, bias_std=0.05)
+    params = case.torch_params()
+    net = ctx.prepare(32, 32, 256, params, prec="bf16")
+    y, x = _t(case.y), _t(case.x)
+    _, g1, _ = net.loss_grad(y, x, params)
+    _, g2, _ = net.loss_grad(y, x, params)
+    for l in range(3):
+        assert torch.equal(g1.w[l], g2.w[l]) and torch.equal(g1.b[l], g2.b[l])
+    xh, saved = net.forward_train(y)
+    gx = (2.0 / 8) * (xh.reshape(8, -1) - x)
+    g3, _ = net.backward(gx.reshape(8, 32, 32), saved, params)
+    for l in range(3):
+        assert _rel(g3.w[l].cpu().numpy(), g1.w[l].cpu().numpy()) <= 1e-6
+    # forward_train returns what recover returns
+    assert torch.equal(xh, net.recover(y))
+    net.free()
+
+
+@pytest.mark.parametrize("prec", ["f32", "bf16"])
+def test_train_step_matches_oracle_adam_and_reduces_loss(dsi, prec):
+    import torch
+
+    import oracle
+    P, ctx = dsi
+    case = make_case(24, 24, 150, 4, cfg_id=27, bias_std=0.02)
+    params = case.torch_params()
+    net = ctx.prepare(24, 24, 150, params, prec=prec)
+    opt = P.AdamState.zeros_like(params)
+    y, x = _t(case.y), _t(case.x)
+    lr = 1e-3
+    w0 = [w.cpu().numpy().astype(np.float64) for w in params.w]
+    _, g_gpu, _ = net.loss_grad(y, x, params)           # the gradient train_step will use (deterministic)
+    g_gpu = [w.cpu().numpy().astype(np.float64) for w in g_gpu.w]
+    loss0 = net.train_step(params, opt, y, x, lr=lr)
+    assert opt.step == 1
+    ref = _oracle_grads(case)
+    assert abs(loss0.item() - ref[0]) <= GTOL[prec] * abs(ref[0])
+    for l in range(3):
+        # the Adam kernel against the oracle's Adam on the same gradient
+        th, _, _ = oracle.adam(w0[l], g_gpu[l], np.zeros_like(w0[l]), np.zeros_like(w0[l]), 1, lr=lr)
+        got = params.w[l].cpu().numpy().astype(np.float64)
+        assert np.abs(got - th).max() <= 1e-6 * lr + 2e-7, (l, np.abs(got - th).max())
+        assert np.abs(got - w0[l]).max() <= lr * 1.001 + 1e-7
+    losses = [loss0.item()]
+    for _ in range(40):
+        losses.append(net.train_step(params, opt, y, x, lr=lr).item())
+    assert opt.step == 41
+    print(prec, "loss", losses[0], "->", losses[-1])
+    assert losses[-1] < 0.7 * losses[0]
+    net.free()
+
+
+def test_metrics_match_oracle(dsi):
+    import oracle
+    P, ctx = dsi
+    import synth
+    B, n = 5, 20
+    x = synth.piecewise_smooth_images(B, n, cfg_id=28).reshape(B, -1)
+    xh = x + synth.normal_values(x.shape, 0.05, 28, 9)
+    xh[1] = x[1] + 0.0 * xh[1]
+    xh[1, :10] += 0.3
+    out = ctx.metrics(_t(xh), _t(x)).cpu().numpy()
+    np.testing.assert_allclose(out[:, 0], ((xh - x) ** 2).sum(axis=1), rtol=1e-6)
+    np.testing.assert_allclose(out[:, 1], oracle.psnr(xh, x), rtol=1e-6)
+    np.testing.assert_allclose(out[:, 2], oracle.relerr(xh, x), rtol=1e-6)
+    np.testing.assert_array_equal(out[:, 3], oracle.success(xh, x))

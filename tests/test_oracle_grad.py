@@ -145,3 +145,18 @@ def test_p18_forward_vs_independent_numpy(orc):
                               for ci in range(C[l])) for co in range(C[l + 1])]) + p.b[l]
             a = np.maximum(z, 0) if l < 2 else z
         np.testing.assert_allclose(xhat[bi], a.reshape(-1), rtol=1e-11, atol=1e-12)
+
+
+def test_backward_from_given_activations_equals_backward(orc):
+    """orc_backward_acts on the oracle's own forward activations reproduces orc_backward
+    bit for bit (so the FD and autograd pins above carry over to it)."""
+    for bias_full, relu_last in ((True, False), (False, True)):
+        net, phi, ws, bs, x, y = _tiny(orc, bias_full, relu_last, seed=3)
+        G = orc.backward(net, phi.T, ws, bs, y, x, want_gy=True)
+        xhat, acts = orc.forward(net, phi.T, ws, bs, y, return_acts=True)
+        _, g = orc.loss(xhat, x)
+        H = orc.backward_acts(net, phi.T, ws, y, acts, g, want_gy=True)
+        for l in range(3):
+            assert np.array_equal(H.w[l], G.w[l])
+            assert np.array_equal(H.b[l], G.b[l])
+        assert np.array_equal(H.y, G.y)
