@@ -125,10 +125,24 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
                            dsi_prec prec, dsi_net **out, void *stream);
 /* Re-pack the network's copies from new parameter values (same shapes). Enqueued on stream. */
 dsi_status dsi_net_update(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, void *stream);
-/* FP8 only: static per-tensor activation scales (host array of L+1 floats:
- * the proxy and the input of every further layer), each a positive power of
- * two; dequantised value = code * scale.  Without this call every scale is 1. */
+/* FP8 only: static per-tensor activation scales (host array of L+1 floats,
+ * the inputs of the proxy layer and of conv layers 1..L: {s_y, s_x~, s_a1,
+ * s_a2}), each a positive power of two; a tensor v is stored as the e4m3
+ * code of v / s.  The FP8 network quantises y (s_y) and the input of conv
+ * layer 2 (s_a1); conv layers 1 and 3 run in BF16, so s_x~ and s_a2 are
+ * unused.  Weight scales are set by dsi_net_prepare from the weights'
+ * largest magnitude.  Without this call (or dsi_net_calibrate) every
+ * activation scale is 1. */
 dsi_status dsi_net_set_act_scales(dsi_net *net, const float *scales_host, int n);
+/* FP8 only: set the activation scales from a calibration batch y [B][M]:
+ * s = 2^ceil(log2(amax / 448)) of y and of conv layer 1's output (computed
+ * by the FP8 proxy and the BF16 conv layer 1).  The scales stay fixed
+ * afterwards, so a result does not depend on the other images of its batch.
+ * Synchronous (waits for `stream`). */
+dsi_status dsi_net_calibrate(dsi_ctx *ctx, dsi_net *net, const float *y, int B, void *stream);
+/* Scales of a network (host array of n floats): {W_fc, W2, s_y, s_x~, s_a1, s_a2}
+ * (weight scales are 1 except for FP8 nets). */
+dsi_status dsi_net_get_scales(const dsi_net *net, float *scales, int n);
 /* Free a prepared network (device memory is released after the device idles). */
 dsi_status dsi_net_free(dsi_ctx *ctx, dsi_net *net);
 /* Query the net's precision and description (host outputs, nullable). */

@@ -191,6 +191,14 @@ class Net:
     def set_act_scales(self, scales):
         _lib.dsi_net_set_act_scales(self.h, list(scales))
 
+    def calibrate(self, y):
+        """FP8 nets: static activation scales from a calibration batch y [B][M]."""
+        _lib.dsi_net_calibrate(self.ctx.h, self.h, _ptr(_f32(y, "y")), y.shape[0], _stream(self.ctx.device))
+
+    def scales(self):
+        """{W_fc, W2, s_y, s_x~, s_a1, s_a2} scales (1 except for FP8 nets)."""
+        return _lib.dsi_net_get_scales(self.h, 6)
+
     def reserve(self, B, train=False):
         _lib.dsi_reserve(self.ctx.h, self.h, B, train)
 

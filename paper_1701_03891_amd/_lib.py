@@ -27,7 +27,8 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_net_prepare", "dsi_net_update", "dsi_net_set_act_scales", "dsi_net_free",
            "dsi_net_info", "dsi_workspace_size", "dsi_reserve", "dsi_recover",
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
-           "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation"]
+           "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation", "dsi_net_calibrate",
+           "dsi_net_get_scales"]
 
 
 class DsiError(RuntimeError):
@@ -91,6 +92,8 @@ def lib() -> ctypes.CDLL:
         "dsi_metrics": (st, [P, P, P, i, i, P, P]),
         "dsi_set_stage_timing": (st, [P, i]),
         "dsi_saved_activation": (st, [P, P, P, z, i, i, P, P]),
+        "dsi_net_calibrate": (st, [P, P, P, i, P]),
+        "dsi_net_get_scales": (st, [P, ctypes.POINTER(ctypes.c_float), i]),
         "dsi_stage_times": (st, [P, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
     }
     for name, (res, args) in sig.items():
@@ -200,3 +203,13 @@ def dsi_stage_times(ctx, nstages=4):
 
 def dsi_saved_activation(ctx, net, saved, saved_bytes, B, layer, out, stream):
     call("dsi_saved_activation", ctx, net, saved, saved_bytes, B, layer, out, stream)
+
+
+def dsi_net_calibrate(ctx, net, y, B, stream):
+    call("dsi_net_calibrate", ctx, net, y, B, stream)
+
+
+def dsi_net_get_scales(net, n=6):
+    arr = (ctypes.c_float * n)()
+    call("dsi_net_get_scales", net, arr, n)
+    return list(arr)

@@ -18,6 +18,7 @@
 
 using dsi::ActView;
 using bf16 = __bf16;
+using u8 = unsigned char;
 
 namespace {
 
@@ -109,6 +110,8 @@ struct dsi_net {
   float *w32[3] = {};                                    // OIHW fp32 copies (backward)
   float *b32[3] = {};                                    // fp32 biases in caller layout (backward)
   void *wp3f = nullptr, *wp2f = nullptr, *wp1f = nullptr;  // packed data-gradient operators
+  float w_scale_fc = 1.0f, w_scale_2 = 1.0f;              // FP8 per-tensor weight scales
+  unsigned *amax_dev = nullptr;                            // FP8: device scratch for amax
   float act_scale[DSI_MAX_LAYERS + 1];
 };
 
@@ -155,6 +158,17 @@ struct Layout {
 Layout layout(const dsi_net &n, int B, int train) {
   Layout L;
   size_t off = 0;
+  if (n.prec == DSI_FP8_E4M3) {
+    const size_t N = (size_t)n.N;
+    L.ypad = off; off += rnd((size_t)B * n.Mpad);
+    L.xt = off; off += rnd((size_t)B * N * 2);
+    L.act[1] = off; off += rnd((size_t)B * 64 * N);
+    L.act[2] = off; off += rnd((size_t)B * 32 * N * 2);
+    L.act[3] = train ? off : SIZE_MAX;
+    if (train) off += rnd((size_t)B * N * 4);
+    L.end = off;
+    return L;
+  }
   const size_t N = (size_t)n.N, es = n.es;
   L.ypad = off; off += rnd((size_t)B * n.Mpad * (n.prec == DSI_F64 ? 8 : 4));
   L.xt = off; off += rnd((size_t)B * N * es);
@@ -198,6 +212,7 @@ void free_net_buffers(dsi_net *n) {
   for (int l = 0; l < DSI_MAX_LAYERS; ++l) { f(n->w[l]); f(n->b[l]); }
   f(n->wp1); f(n->wp2); f(n->wp3);
   f(n->wp3f); f(n->wp2f); f(n->wp1f);
+  { void *a = n->amax_dev; f(a); n->amax_dev = nullptr; }
   for (int l = 0; l < 3; ++l) {
     void *a = n->bp[l]; f(a); n->bp[l] = nullptr;
     void *c = n->w32[l]; f(c); n->w32[l] = nullptr;
@@ -209,6 +224,44 @@ dsi_status alloc(void **p, size_t bytes) {
   if (hipMalloc(p, std::max<size_t>(bytes, 16)) != hipSuccess) {
     *p = nullptr;
     return fail(DSI_E_NOMEM, "allocation of %zu bytes failed", bytes);
+  }
+  return DSI_OK;
+}
+
+// power-of-two scale so that amax / scale fits the e4m3 range [-448, 448]
+float pow2_scale(float amax) {
+  if (!(amax > 0.0f) || !std::isfinite(amax)) return 1.0f;
+  return std::ldexp(1.0f, (int)std::ceil(std::log2((double)amax / 448.0)));
+}
+
+dsi_status device_amax(dsi_net *n, const float *x, long count, hipStream_t s, float *out) {
+  HIPCHK(dsi::amax_f32(x, count, n->amax_dev, s));
+  unsigned bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, n->amax_dev, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  memcpy(out, &bits, 4);
+  return DSI_OK;
+}
+
+// FP8 net: W_fc and W2 as e4m3 codes with power-of-two per-tensor scales (synchronous:
+// the scales are host values), W1, W3 as BF16 (layers 1 and 3 run in BF16).
+dsi_status pack_params_fp8(dsi_net *n, const dsi_params *p, hipStream_t s) {
+  const dsi_net_desc &d = n->d;
+  const int N = n->N;
+  float a_fc = 0.0f, a_2 = 0.0f;
+  dsi_status st;
+  if ((st = device_amax(n, p->w_fc, (long)N * d.M, s, &a_fc)) != DSI_OK) return st;
+  if ((st = device_amax(n, p->w[1], wcount(d, 1), s, &a_2)) != DSI_OK) return st;
+  n->w_scale_fc = pow2_scale(a_fc);
+  n->w_scale_2 = pow2_scale(a_2);
+  HIPCHK(dsi::pack_fc_fp8(p->w_fc, (u8 *)n->wfc, N, d.M, n->Mpad, 1.0f / n->w_scale_fc, s));
+  HIPCHK(dsi::pack_first(p->w[0], n->wp1, 64, 0, 1, s));
+  HIPCHK(dsi::pack_mid_fp8(p->w[1], (u8 *)n->wp2, 1.0f / n->w_scale_2, s));
+  HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, 1, s));
+  for (int l = 0; l < 3; ++l) {
+    const int C = d.C[l + 1];
+    if (d.bias_per_pixel && C > 1) HIPCHK(dsi::pack_bias_hwc(p->b[l], n->bp[l], C, N, s));
+    else HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
   }
   return DSI_OK;
 }
@@ -227,6 +280,7 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
     }
     return DSI_OK;
   }
+  if (n->prec == DSI_FP8_E4M3) return pack_params_fp8(n, p, s);
   HIPCHK(dsi::pack_fc(p->w_fc, n->wfc, N, d.M, n->Mpad, pr, s));
   if (n->wfcT) {
     (void)hipFree(n->wfcT);
@@ -281,7 +335,7 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     return DSI_OK;
   }
   // proxy x~ = W_fc y (K padded to Mpad with zeros)
-  const bool direct_y = (M % 16 == 0) && aligned16(y);
+  const bool direct_y = ((M % 16 == 0) && aligned16(y)) || n->prec == DSI_FP8_E4M3;
   const float *yk = y;
   long ldy = M;
   if (!direct_y) {
@@ -305,6 +359,24 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
           o, ActView{d.C[l + 1], H, W, 0}, B, d.k[l], s)));
       a = o;
     }
+  } else if (n->prec == DSI_FP8_E4M3) {
+    // y -> e4m3 codes (scale s_y), FP8 proxy GEMM -> x~ BF16, conv1 BF16 -> a1 e4m3 codes (scale s_a1),
+    // conv2 FP8 -> a2 BF16, conv3 BF16
+    const float sy = n->act_scale[0], sa1 = n->act_scale[2];
+    u8 *yq = at<u8>(base, L.ypad), *a1 = at<u8>(base, L.act[1]);
+    bf16 *xt = at<bf16>(base, L.xt), *a2 = at<bf16>(base, L.act[2]);
+    HIPCHK(dsi::quant_rows(y, yq, B, M, n->Mpad, 1.0f / sy, s));
+    HIPCHK(dsi::gemm_nt_fp8(yq, n->Mpad, (const u8 *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, n->w_scale_fc * sy, s));
+    clk.mark();
+    HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, u8>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
+                                                               nullptr, a1, B, H, W, s, 1.0f / sa1)));
+    clk.mark();
+    HIPCHK((dsi::conv_mid<u8, 64, 32, dsi::EPI_BIAS, bf16>(a1, (const u8 *)n->wp2, n->bp[1], d.bias_per_pixel, 1,
+                                                           nullptr, a2, B, H, W, s, n->w_scale_2 * sa1)));
+    clk.mark();
+    HIPCHK((dsi::conv_last<bf16, 32>)(a2, (const bf16 *)n->wp3, n->bp[2], d.bias_per_pixel, d.relu_last,
+                                      xout_last, B, H, W, s));
+    clk.mark();
   } else if (n->prec == DSI_BF16) {
     bf16 *xt = at<bf16>(base, L.xt), *a1 = at<bf16>(base, L.act[1]), *a2 = at<bf16>(base, L.act[2]);
     HIPCHK(dsi::gemm_nt_bf16_out_bf16(yk, ldy, (const bf16 *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
@@ -558,7 +630,6 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
     return fail(DSI_E_DTYPE, "unknown precision %d", (int)prec);
   if ((prec == DSI_BF16 || prec == DSI_FP8_E4M3) && !paper)
     return fail(DSI_E_DTYPE, "BF16/FP8 need the paper's architecture (C = 1,64,32,1; k = 11)");
-  if (prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "FP8 path not built in this version");
   if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
   dsi_net *n = new (std::nothrow) dsi_net;
   if (!n) return fail(DSI_E_NOMEM, "host allocation failed");
@@ -566,7 +637,7 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
   n->prec = prec;
   n->path = (paper && prec != DSI_F64) ? PATH_PAPER : PATH_GENERIC;
   n->N = desc->n1 * desc->n2;
-  n->Mpad = prec == DSI_F64 ? desc->M : (desc->M + 15) / 16 * 16;
+  n->Mpad = prec == DSI_F64 ? desc->M : prec == DSI_FP8_E4M3 ? (desc->M + 63) / 64 * 64 : (desc->M + 15) / 16 * 16;
   n->es = elem_size(prec);
   for (int q = 0; q <= DSI_MAX_LAYERS; ++q) n->act_scale[q] = 1.0f;
   const dsi_net_desc &d = *desc;
@@ -577,6 +648,12 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
       A(&n->w[l], wcount(d, l) * n->es);
       A(&n->b[l], bcount(d, l) * n->es);
     }
+  } else if (prec == DSI_FP8_E4M3) {
+    A(&n->wp1, (size_t)11 * 2 * 64 * 8 * 2);
+    A(&n->wp2, (size_t)64 * 32 * 121);
+    A(&n->wp3, (size_t)32 * 121 * 2);
+    A((void **)&n->amax_dev, 256);
+    for (int l = 0; l < 3; ++l) A((void **)&n->bp[l], bcount(d, l) * 4);
   } else {
     A(&n->wp1, (size_t)11 * 2 * 64 * 8 * n->es);
     A(&n->wp2, (size_t)64 * 32 * 121 * n->es);
@@ -620,6 +697,48 @@ dsi_status dsi_net_set_act_scales(dsi_net *net, const float *scales, int n) {
       return fail(DSI_E_SHAPE, "scale %d = %g is not a positive power of two", q, scales[q]);
   }
   for (int q = 0; q < n; ++q) net->act_scale[q] = scales[q];
+  return DSI_OK;
+}
+
+dsi_status dsi_net_calibrate(dsi_ctx *ctx, dsi_net *net, const float *y, int B, void *stream) {
+  if (!ctx || !net || !y) return fail(DSI_E_NULL, "ctx, net and y must be non-NULL");
+  if (net->prec != DSI_FP8_E4M3) return fail(DSI_E_STATE, "calibration applies to FP8 nets only");
+  if (B < 1) return fail(DSI_E_SHAPE, "B = %d", B);
+  if (!aligned16(y)) return fail(DSI_E_ALIGN, "y must be 16-byte aligned");
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  hipStream_t s = (hipStream_t)stream;
+  const dsi_net_desc &d = net->d;
+  const int N = net->N, H = d.n1, W = d.n2, M = d.M;
+  const Layout L = layout(*net, B, 0);
+  const size_t a1_bf16 = rnd((size_t)B * 64 * N * 2);
+  dsi_status st = ensure_ws(ctx, L.end + a1_bf16);
+  if (st != DSI_OK) return st;
+  float ay = 0.0f;
+  if ((st = device_amax(net, y, (long)B * M, s, &ay)) != DSI_OK) return st;
+  const float sy = pow2_scale(ay);
+  u8 *yq = at<u8>(ctx->ws, L.ypad);
+  bf16 *xt = at<bf16>(ctx->ws, L.xt), *a1 = at<bf16>(ctx->ws, L.end);
+  HIPCHK(dsi::quant_rows(y, yq, B, M, net->Mpad, 1.0f / sy, s));
+  HIPCHK(dsi::gemm_nt_fp8(yq, net->Mpad, (const u8 *)net->wfc, net->Mpad, xt, N, B, N, net->Mpad, net->w_scale_fc * sy, s));
+  HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, bf16>(xt, (const bf16 *)net->wp1, net->bp[0], d.bias_per_pixel,
+                                                                1, nullptr, a1, B, H, W, s)));
+  HIPCHK(dsi::amax_bf16(a1, (long)B * 64 * N, net->amax_dev, s));
+  unsigned bits = 0;
+  HIPCHK(hipMemcpyAsync(&bits, net->amax_dev, 4, hipMemcpyDeviceToHost, s));
+  HIPCHK(hipStreamSynchronize(s));
+  float aa1;
+  memcpy(&aa1, &bits, 4);
+  net->act_scale[0] = sy;
+  net->act_scale[2] = pow2_scale(aa1);
+  return DSI_OK;
+}
+
+dsi_status dsi_net_get_scales(const dsi_net *net, float *scales, int n) {
+  if (!net || !scales) return fail(DSI_E_NULL, "net and scales must be non-NULL");
+  if (n < 2) return fail(DSI_E_SHAPE, "n = %d", n);
+  scales[0] = net->w_scale_fc;
+  scales[1] = net->w_scale_2;
+  for (int q = 2; q < n && q - 2 <= net->d.L; ++q) scales[q] = net->act_scale[q - 2];
   return DSI_OK;
 }
 
@@ -671,6 +790,7 @@ dsi_status dsi_recover(dsi_ctx *ctx, const dsi_net *net, const float *y, float *
 dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
                              void *saved, size_t saved_bytes, void *stream) {
   if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1 for training", B);
   if (!y || !xhat || !saved) return fail(DSI_E_NULL, "y, xhat and saved must be non-NULL");
   if (!aligned16(y) || !aligned16(xhat) || !aligned16(saved)) return fail(DSI_E_ALIGN, "buffers must be 16-byte aligned");
@@ -724,6 +844,7 @@ dsi_status ensure_wfcT(dsi_net *n, hipStream_t s) {
 dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, const void *saved,
                         size_t saved_bytes, int B, const dsi_grads *grads, float *gy, void *stream) {
   if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
   if (!gxhat || !saved) return fail(DSI_E_NULL, "gxhat and saved must be non-NULL");
   dsi_status st = check_grads(net, grads);
@@ -842,6 +963,7 @@ extern "C" {
 dsi_status dsi_loss_grad(dsi_ctx *ctx, dsi_net *net, const float *y, const float *x, int B, const dsi_grads *grads,
                          float *gy, double *loss_dev, void *stream) {
   if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
   if (!y || !x) return fail(DSI_E_NULL, "y and x must be non-NULL");
   if (!aligned16(y) || !aligned16(x)) return fail(DSI_E_ALIGN, "y and x must be 16-byte aligned");
@@ -854,6 +976,7 @@ dsi_status dsi_loss_grad(dsi_ctx *ctx, dsi_net *net, const float *y, const float
 dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, dsi_adam *opt, const float *y,
                           const float *x, int B, float lr, double *loss_dev, void *stream) {
   if (!ctx || !net || !opt) return fail(DSI_E_NULL, "ctx, net and opt must be non-NULL");
+  if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
   if (!y || !x) return fail(DSI_E_NULL, "y and x must be non-NULL");
   dsi_status st = check_params(net->d, params);

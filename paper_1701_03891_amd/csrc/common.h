@@ -97,6 +97,13 @@ template <> struct Frag8<float> {
   }
 };
 
+// FP8 e4m3 (stored as bytes): 32 consecutive K elements per lane, one
+// 32x32x64 MFMA per fragment pair.
+template <> struct Frag8<u8> {
+  i32x8 v;
+  DSI_INLINE void mma(const Frag8 &b, f32x16 &acc) const { acc = mfma_fp8(v, b.v, acc); }
+};
+
 template <typename T> DSI_INLINE Frag8<T> frag_load(const T *p);  // p 16-byte aligned
 template <> DSI_INLINE Frag8<bf16> frag_load<bf16>(const bf16 *p) {
   Frag8<bf16> f;
@@ -107,6 +114,12 @@ template <> DSI_INLINE Frag8<float> frag_load<float>(const float *p) {
   Frag8<float> f;
   f.lo = *reinterpret_cast<const f32x4 *>(p);
   f.hi = *reinterpret_cast<const f32x4 *>(p + 4);
+  return f;
+}
+template <> DSI_INLINE Frag8<u8> frag_load<u8>(const u8 *p) {
+  Frag8<u8> f;
+  const i32x4 lo = *reinterpret_cast<const i32x4 *>(p), hi = *reinterpret_cast<const i32x4 *>(p + 16);
+  f.v = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
   return f;
 }
 template <typename T> DSI_INLINE Frag8<T> frag_zero() {

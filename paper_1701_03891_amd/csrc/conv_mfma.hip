@@ -42,10 +42,26 @@ template <> DSI_INLINE Frag8<float> lds_frag<float>(const unsigned char *p, int 
   f.hi = *reinterpret_cast<const f32x4 *>(p + plane);
   return f;
 }
+template <> DSI_INLINE Frag8<u8> lds_frag<u8>(const unsigned char *p, int plane) {
+  Frag8<u8> f;
+  const i32x4 lo = *reinterpret_cast<const i32x4 *>(p), hi = *reinterpret_cast<const i32x4 *>(p + plane);
+  f.v = i32x8{lo[0], lo[1], lo[2], lo[3], hi[0], hi[1], hi[2], hi[3]};
+  return f;
+}
+
+// channels per HBM slice of a blocked activation tensor: 16 (bf16, fp32) or 64 (fp8)
+template <typename T> constexpr int slice_ch() { return sizeof(T) == 1 ? 64 : 16; }
 
 template <typename TO> DSI_INLINE void store4(TO *dst, float a, float b, float c, float d);
 template <> DSI_INLINE void store4<float>(float *dst, float a, float b, float c, float d) {
   *reinterpret_cast<f32x4 *>(dst) = f32x4{a, b, c, d};
+}
+// FP8: saturate to the e4m3 range, then the hardware round-to-nearest-even conversion
+template <> DSI_INLINE void store4<u8>(u8 *dst, float a, float b, float c, float d) {
+  auto sat = [](float v) { return fminf(fmaxf(v, -448.0f), 448.0f); };
+  int lo = __builtin_amdgcn_cvt_pk_fp8_f32(sat(a), sat(b), 0, false);
+  int w = __builtin_amdgcn_cvt_pk_fp8_f32(sat(c), sat(d), lo, true);
+  *reinterpret_cast<int *>(dst) = w;
 }
 template <> DSI_INLINE void store4<bf16>(bf16 *dst, float a, float b, float c, float d) {
   bf16x4 v;
@@ -63,19 +79,22 @@ template <> DSI_INLINE void load4f<bf16>(const bf16 *src, float *o) {
 }
 
 // ===================================================================== conv_mid
-// in   [B][CIN/16][H][W][16]  (T)
-// wp   [CIN/16][11 v][11 u][COUT/32][64 lanes][8]  (T): lane l holds
-//      W[co = ct*32 + l%32][ci = cs*16 + (l/32)*8 + e][u][v]
-// EPI_BIAS: out = ReLU?(acc + bias); bias per pixel [H][W][COUT] or per channel [COUT] (fp32)
+// in   [B][CIN/SC][H][W][SC]  (T; SC = 16 channels per slice, 64 for FP8)
+// wp   [CIN/SC][11 v][11 u][COUT/32][64 lanes][FE]  (T; FE = 8, 32 for FP8): lane l holds
+//      W[co = ct*32 + l%32][ci = cs*SC + (l/32)*FE + e][u][v]
+// EPI_BIAS: out = ReLU?(oscale * acc + bias); bias per pixel [H][W][COUT] or per channel [COUT] (fp32)
 // EPI_MASK: out = acc * (mask > 0), mask in the output layout (backward through ReLU)
+// oscale dequantises FP8 products (weight scale x activation scale); 1 otherwise.
 template <typename T, int CIN, int COUT, int ROWS, int EPI, typename TO>
 __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in, const T *__restrict__ wp,
                                                        const float *__restrict__ bias, int bias_pp, int relu,
                                                        const T *__restrict__ mask, TO *__restrict__ out,
-                                                       int H, int W, int tiles_w, int tiles_per_img) {
+                                                       int H, int W, int tiles_w, int tiles_per_img, float oscale) {
   constexpr int TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
-  constexpr int CH16 = (int)sizeof(T);       // 16-byte chunks per pixel per slice: bf16 2, fp32 4
-  constexpr int NCT = COUT / 32, NCS = CIN / 16;
+  constexpr int SC = slice_ch<T>();
+  constexpr int CH16 = SC * (int)sizeof(T) / 16;  // 16-byte chunks per pixel per slice: bf16 2, fp32 4, fp8 4
+  constexpr int FE = 16 * (CH16 / 2) / (int)sizeof(T);  // fragment elements per lane: 8, 8, 32
+  constexpr int NCT = COUT / 32, NCS = CIN / SC;
   constexpr int PLANE = LW * 16;              // bytes between chunk planes of one LDS row
   __shared__ __attribute__((aligned(16))) unsigned char lds[LH * CH16 * PLANE];
 
@@ -93,24 +112,24 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
 
   for (int cs = 0; cs < NCS; ++cs) {
     __syncthreads();  // previous slice fully consumed
-    const T *src = in + (long)(img * NCS + cs) * H * W * 16;
+    const T *src = in + (long)(img * NCS + cs) * H * W * SC;
     for (int idx = tid; idx < LH * LW * CH16; idx += 256) {
       const int chunk = idx / (LH * LW), pix = idx - chunk * (LH * LW);
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
       i32x4 val = {0, 0, 0, 0};
       if (gi >= 0 && gi < H && gj >= 0 && gj < W)
-        val = *reinterpret_cast<const i32x4 *>(src + ((long)gi * W + gj) * 16 + chunk * (16 / (int)sizeof(T)));
+        val = *reinterpret_cast<const i32x4 *>(src + ((long)gi * W + gj) * SC + chunk * (16 / (int)sizeof(T)));
       *reinterpret_cast<i32x4 *>(lds + (row * CH16 + chunk) * PLANE + col * 16) = val;
     }
     __syncthreads();
-    const T *wcs = wp + (long)cs * KT * KT * NCT * 512 + lane * 8;
+    const T *wcs = wp + (long)cs * KT * KT * NCT * 64 * FE + lane * FE;
     for (int v = 0; v < KT; ++v) {
       Frag8<T> wf[KT][NCT];
 #pragma unroll
       for (int u = 0; u < KT; ++u)
 #pragma unroll
-        for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + ((v * KT + u) * NCT + c) * 512);
+        for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + ((v * KT + u) * NCT + c) * 64 * FE);
       const unsigned char *lrow = lds + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + (px + v) * 16;
 #pragma unroll
       for (int rr = 0; rr < ROWS + 2 * RAD; ++rr) {
@@ -141,7 +160,7 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
         const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
         float vals[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vals[e] = acc[i][c][4 * q + e];
+        for (int e = 0; e < 4; ++e) vals[e] = acc[i][c][4 * q + e] * oscale;
         if constexpr (EPI == EPI_BIAS) {
           float bv[4];
           load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
@@ -169,11 +188,13 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
 // The B operand of the k-step for filter row u is 8 consecutive pixels of one
 // LDS row, read with one unaligned 16-byte LDS load.
 // EPI_BIAS: out = ReLU?(acc + bias);  EPI_MASK: out = acc * (mask > 0).
+// An FP8 output (TO = u8) is quantised as code = e4m3(oscale * value) into 64-channel slices.
 template <typename T, int COUT, int EPI, typename TI, typename TO>
 __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ in, const T *__restrict__ wp,
                                                          const float *__restrict__ bias, int bias_pp, int relu,
                                                          const T *__restrict__ mask, TO *__restrict__ out,
-                                                         int H, int W, int tiles_w, int tiles_per_img) {
+                                                         int H, int W, int tiles_w, int tiles_per_img, float oscale) {
+  constexpr int OSC = slice_ch<TO>();
   constexpr int ROWS = 4, TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
   constexpr int LWA = LW + 8;  // zero columns so the 8-wide reads of the last lanes stay in the tile
   constexpr int NCT = COUT / 32;
@@ -220,7 +241,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int co0 = c * 32 + 8 * q + 4 * h;
-        const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
+        const long o = ((((long)img * (COUT / OSC) + co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC;
         float vals[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) vals[e] = acc[c][4 * q + e];
@@ -237,6 +258,10 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
           load4f<T>(mask + o, mv);
 #pragma unroll
           for (int e = 0; e < 4; ++e) vals[e] = mv[e] > 0.0f ? vals[e] : 0.0f;
+        }
+        if constexpr (sizeof(TO) == 1) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e) vals[e] *= oscale;
         }
         store4<TO>(out + o, vals[0], vals[1], vals[2], vals[3]);
       }
@@ -342,23 +367,24 @@ static inline void tiles(int H, int W, int TH, int TW, int &tw, int &tpi) {
 
 template <typename T, int COUT, int EPI, typename TI, typename TO>
 hipError_t conv_first(const TI *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
-                      TO *out, int B, int H, int W, hipStream_t s) {
+                      TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
   int tw, tpi;
   tiles(H, W, 16, 32, tw, tpi);
-  conv_first_kernel<T, COUT, EPI, TI, TO><<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi);
+  conv_first_kernel<T, COUT, EPI, TI, TO>
+      <<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
   return hipGetLastError();
 }
 
 template <typename T, int CIN, int COUT, int EPI, typename TO>
 hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
-                    TO *out, int B, int H, int W, hipStream_t s) {
+                    TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
   constexpr int ROWS = COUT == 32 ? 8 : 4;
   int tw, tpi;
   tiles(H, W, 4 * ROWS, 32, tw, tpi);
   conv_mid_kernel<T, CIN, COUT, ROWS, EPI, TO>
-      <<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi);
+      <<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
   return hipGetLastError();
 }
 
@@ -372,16 +398,18 @@ hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, in
   return hipGetLastError();
 }
 
-template hipError_t conv_first<bf16, 64, EPI_BIAS, bf16, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
-template hipError_t conv_first<float, 64, EPI_BIAS, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
-template hipError_t conv_mid<bf16, 64, 32, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
-template hipError_t conv_mid<float, 64, 32, EPI_BIAS, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
-template hipError_t conv_first<bf16, 32, EPI_MASK, float, bf16>(const float *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
-template hipError_t conv_first<float, 32, EPI_MASK, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
-template hipError_t conv_mid<bf16, 32, 64, EPI_MASK, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t);
-template hipError_t conv_mid<float, 32, 64, EPI_MASK, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t);
+template hipError_t conv_first<bf16, 64, EPI_BIAS, bf16, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_first<float, 64, EPI_BIAS, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<bf16, 64, 32, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<float, 64, 32, EPI_BIAS, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t, float);
+template hipError_t conv_first<bf16, 32, EPI_MASK, float, bf16>(const float *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_first<float, 32, EPI_MASK, float, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<bf16, 32, 64, EPI_MASK, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<float, 32, 64, EPI_MASK, float>(const float *, const float *, const float *, int, int, const float *, float *, int, int, int, hipStream_t, float);
 template hipError_t conv_last<bf16, 64>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
 template hipError_t conv_last<float, 64>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
+template hipError_t conv_first<bf16, 64, EPI_BIAS, bf16, u8>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, u8 *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<u8, 64, 32, EPI_BIAS, bf16>(const u8 *, const u8 *, const float *, int, int, const u8 *, bf16 *, int, int, int, hipStream_t, float);
 template hipError_t conv_last<bf16, 32>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
 template hipError_t conv_last<float, 32>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
 

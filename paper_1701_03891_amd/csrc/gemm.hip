@@ -91,6 +91,43 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const TX *__restrict__ X, 
   }
 }
 
+// FP8 e4m3 variant: C[b][o] = oscale * sum_k Xq[b][k] Wq[o][k], both operands FP8 codes,
+// rows padded with zero codes to K % 64 == 0 and 16-byte aligned; one 32x32x64
+// MFMA per 64-wide K step (a lane holds 32 consecutive K codes).
+__global__ __launch_bounds__(256) void gemm_nt_fp8_kernel(const u8 *__restrict__ X, long ldx, const u8 *__restrict__ W,
+                                                          long ldw, bf16 *__restrict__ C, long ldc, int Bn, int O,
+                                                          int K, float oscale) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int b0 = blockIdx.y * 64 + (wave >> 1) * 32;
+  const int o0 = blockIdx.x * 64 + (wave & 1) * 32;
+  if (b0 >= Bn || o0 >= O) return;
+  const int rb = min(b0 + (lane & 31), Bn - 1), ro = min(o0 + (lane & 31), O - 1);
+  const int kh = (lane >> 5) * 32;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  const u8 *px = X + (long)rb * ldx + kh, *pw = W + (long)ro * ldw + kh;
+  for (int k0 = 0; k0 < K; k0 += 64) {
+    Frag8<u8> fx = frag_load<u8>(px + k0), fw = frag_load<u8>(pw + k0);
+    fx.mma(fw, acc);
+  }
+  const int o = o0 + (lane & 31);
+  if (o >= O) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = b0 + mfma_row(lane, r);
+    if (b < Bn) C[(long)b * ldc + o] = (bf16)(acc[r] * oscale);
+  }
+}
+
+hipError_t gemm_nt_fp8(const u8 *X, long ldx, const u8 *W, long ldw, bf16 *C, long ldc, int Bn, int O, int K,
+                       float oscale, hipStream_t s) {
+  if (Bn <= 0 || O <= 0) return hipSuccess;
+  dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
+  gemm_nt_fp8_kernel<<<grid, 256, 0, s>>>(X, ldx, W, ldw, C, ldc, Bn, O, K, oscale);
+  return hipGetLastError();
+}
+
 // FP64 reference-precision variant (VALU), for the DSI_F64 checking path.
 __global__ __launch_bounds__(256) void gemm_nt_f64_kernel(const double *__restrict__ X, long ldx,
                                                           const double *__restrict__ W, long ldw,

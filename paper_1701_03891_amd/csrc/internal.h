@@ -44,10 +44,10 @@ hipError_t bias_grad(const TG *gz, ActView vg, int B, int per_pixel, TD *db, hip
 // conv_mfma.hip (the paper's 1 -> 64 -> 32 -> 1, 11 x 11 network)
 template <typename T, int COUT, int EPI, typename TI, typename TO>
 hipError_t conv_first(const TI *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
-                      TO *out, int B, int H, int W, hipStream_t s);
+                      TO *out, int B, int H, int W, hipStream_t s, float oscale = 1.0f);
 template <typename T, int CIN, int COUT, int EPI, typename TO>
 hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
-                    TO *out, int B, int H, int W, hipStream_t s);
+                    TO *out, int B, int H, int W, hipStream_t s, float oscale = 1.0f);
 template <typename T, int CIN>
 hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, int relu, float *out, int B,
                      int H, int W, hipStream_t s);
@@ -87,4 +87,15 @@ size_t conv_wgrad_thin_partial_floats(int CW, int nchunk);
 template <typename TT>
 hipError_t conv_wgrad_thin(int mode, const __bf16 *wide, const TT *thin, int CW, float *partial, int nchunk, float *dw,
                            int B, int H, int W, hipStream_t s);
+}  // namespace dsi
+
+namespace dsi {
+// FP8 e4m3 path (gemm.hip, misc.hip)
+hipError_t gemm_nt_fp8(const unsigned char *X, long ldx, const unsigned char *W, long ldw, __bf16 *C, long ldc,
+                       int Bn, int O, int K, float oscale, hipStream_t s);
+hipError_t amax_f32(const float *x, long n, unsigned *out, hipStream_t s);
+hipError_t amax_bf16(const __bf16 *x, long n, unsigned *out, hipStream_t s);
+hipError_t quant_rows(const float *in, unsigned char *out, int B, int M, int Mpad, float inv_scale, hipStream_t s);
+hipError_t pack_mid_fp8(const float *w, unsigned char *out, float inv_scale, hipStream_t s);
+hipError_t pack_fc_fp8(const float *w, unsigned char *out, int N, int M, int Mpad, float inv_scale, hipStream_t s);
 }  // namespace dsi

@@ -1,5 +1,7 @@
 // misc.hip -- weight packing, casts, the loss and its gradient, Sec. 5
 // metrics, and the Adam update (Kingma & Ba).
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -129,6 +131,91 @@ hipError_t pad_rows(const float *in, void *out, int B, int M, int Mpad, int prec
   if (n <= 0) return hipSuccess;
   if (prec == 1) pad_rows_kernel<bf16><<<GRID1(n), 0, s>>>(in, (bf16 *)out, B, M, Mpad);
   else pad_rows_kernel<float><<<GRID1(n), 0, s>>>(in, (float *)out, B, M, Mpad);
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------------- FP8
+// max |x| over n floats into *out (as the bit pattern of a non-negative float,
+// whose unsigned order is the float order); *out must start at 0.
+__global__ void amax_kernel(const float *__restrict__ x, long n, unsigned *__restrict__ out) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) m = fmaxf(m, fabsf(x[i]));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+template <typename T>
+__global__ void amax_any_kernel(const T *__restrict__ x, long n, unsigned *__restrict__ out) {
+  __shared__ float red[256];
+  float m = 0.0f;
+  for (long i = (long)blockIdx.x * 256 + threadIdx.x; i < n; i += (long)gridDim.x * 256) m = fmaxf(m, fabsf(to_f32(x[i])));
+  red[threadIdx.x] = m;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (threadIdx.x < h) red[threadIdx.x] = fmaxf(red[threadIdx.x], red[threadIdx.x + h]);
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) atomicMax(out, __float_as_uint(red[0]));
+}
+__global__ void zero_u32_kernel(unsigned *p) { *p = 0u; }
+
+hipError_t amax_f32(const float *x, long n, unsigned *out, hipStream_t s) {
+  zero_u32_kernel<<<1, 1, 0, s>>>(out);
+  const long blocks = std::min<long>(1024, (n + 255) / 256);
+  if (n > 0) amax_kernel<<<(unsigned)blocks, 256, 0, s>>>(x, n, out);
+  return hipGetLastError();
+}
+hipError_t amax_bf16(const bf16 *x, long n, unsigned *out, hipStream_t s) {
+  zero_u32_kernel<<<1, 1, 0, s>>>(out);
+  const long blocks = std::min<long>(1024, (n + 255) / 256);
+  if (n > 0) amax_any_kernel<bf16><<<(unsigned)blocks, 256, 0, s>>>(x, n, out);
+  return hipGetLastError();
+}
+
+// rows [B][M] fp32 -> FP8 codes [B][Mpad] of in * inv_scale, zero-padded
+__global__ void quant_rows_kernel(const float *__restrict__ in, u8 *__restrict__ out, int B, int M, int Mpad,
+                                  float inv_scale) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)B * Mpad) return;
+  const int b = (int)(idx / Mpad), m = (int)(idx % Mpad);
+  out[idx] = m < M ? f32_to_e4m3(in[(long)b * M + m] * inv_scale) : (u8)0;
+}
+hipError_t quant_rows(const float *in, u8 *out, int B, int M, int Mpad, float inv_scale, hipStream_t s) {
+  const long n = (long)B * Mpad;
+  if (n > 0) quant_rows_kernel<<<GRID1(n), 0, s>>>(in, out, B, M, Mpad, inv_scale);
+  return hipGetLastError();
+}
+
+// W2 [32][64][11][11] fp32 -> FP8 codes [11 v][11 u][64 lanes][32]: lane l holds
+// W[co = l%32][ci = 32*(l/32) + e][u][v] * inv_scale (one 64-channel slice, one tile of 32 outputs)
+__global__ void pack_mid_fp8_kernel(const float *__restrict__ w, u8 *__restrict__ out, float inv_scale) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= 32 * 64 * 121) return;
+  const int e = idx & 31, lane = (idx >> 5) & 63, u = (idx >> 11) % 11, v = (idx >> 11) / 11;
+  const int co = lane & 31, ci = 32 * (lane >> 5) + e;
+  out[idx] = f32_to_e4m3(w[(((long)co * 64 + ci) * 11 + u) * 11 + v] * inv_scale);
+}
+hipError_t pack_mid_fp8(const float *w, u8 *out, float inv_scale, hipStream_t s) {
+  pack_mid_fp8_kernel<<<GRID1(32 * 64 * 121), 0, s>>>(w, out, inv_scale);
+  return hipGetLastError();
+}
+
+// W_fc [N][M] fp32 -> FP8 codes [N][Mpad] (zero-padded)
+__global__ void pack_fc_fp8_kernel(const float *__restrict__ w, u8 *__restrict__ out, int N, int M, int Mpad,
+                                   float inv_scale) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)N * Mpad) return;
+  const int p = (int)(idx / Mpad), m = (int)(idx % Mpad);
+  out[idx] = m < M ? f32_to_e4m3(w[(long)p * M + m] * inv_scale) : (u8)0;
+}
+hipError_t pack_fc_fp8(const float *w, u8 *out, int N, int M, int Mpad, float inv_scale, hipStream_t s) {
+  const long n = (long)N * Mpad;
+  pack_fc_fp8_kernel<<<GRID1(n), 0, s>>>(w, out, N, M, Mpad, inv_scale);
   return hipGetLastError();
 }
 

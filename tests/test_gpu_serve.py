@@ -1,0 +1,40 @@
+"""Serving loop on the GPU: graph-replayed batches of mixed networks overlap on
+two streams, and every request's result is bit-identical to recovering that
+request alone (per-image results do not depend on the batch they run in)."""
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def test_served_results_equal_results_alone():
+    import torch
+
+    import paper_1701_03891_amd as P
+    from paper_1701_03891_amd import serve
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    nets, phis = serve.make_workload(sizes=(32, 64), ratios=(0.10, 0.25))
+    buckets = (1, 2, 4, 8, 16, 32, 64)
+    ex = serve.GraphExecutor(nets, n_slots=2, buckets=buckets)
+    reqs = serve.make_requests(nets, phis, 300, qps=20000.0, max_images=24)
+    srv = serve.Server(ex, len(nets), buckets, budget=8 << 30)
+    stats = srv.run(reqs)
+    torch.cuda.synchronize()
+    print("serving:", stats)
+    assert all(r.finish is not None for r in reqs)
+    assert stats["max_concurrent_batches"] == 2
+    assert stats["mean_batch"] > 1.5        # requests were merged
+    ctx = P.Context(0)
+    alone = [ctx.prepare(*shape, params, prec=prec) for shape, params, prec in nets]
+    mism = 0
+    for r in reqs:
+        ref = alone[r.net].recover(r.y)
+        if not torch.equal(ref, r.out):
+            mism += 1
+    for a in alone:
+        a.free()
+    ctx.close()
+    ex.close()
+    assert mism == 0, f"{mism} requests differ from their results alone"
+    assert stats["p99_ms"] >= stats["p50_ms"] > 0
