@@ -107,7 +107,15 @@ def time_path(ctx, net, y, steps, warmup, torch, stage_timing):
     return dict(total_ms=total_ms, wall_s=wall, per_step_ms=per, stages=stages, xhat=xh)
 
 
-def cpu_baseline(phi, x, prm, y_host, xh_bf16, xh_f32, n_img):
+def calibration_y(ctx, P, torch, phi, B=64):
+    """Measurements of a separate seeded calibration batch (FP8 static activation scales)."""
+    import synth
+    xc = synth.piecewise_smooth_images(B, N1, N2, cfg_id=900, stream=synth.STREAM_CALIB).reshape(B, -1)
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda:0")  # noqa: E731
+    return ctx.measure(t(phi), t(xc))
+
+
+def cpu_baseline(phi, x, prm, y_host, xhs, n_img):
     """The FP64 oracle on the first n_img images of the batch, on this host's cores."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
@@ -123,7 +131,7 @@ def cpu_baseline(phi, x, prm, y_host, xh_bf16, xh_f32, n_img):
            "sample": f"{n_img} of the 256 images of the batch (64x64, M=1024), FP64 C oracle, "
                      f"{dt:.1f} s on {threads} threads"}
     acc = {}
-    for name, xh in (("bf16", xh_bf16), ("f32", xh_f32)):
+    for name, xh in xhs.items():
         xh = xh[:n_img].reshape(n_img, -1).astype(np.float64)
         rel = oracle.relerr(xh, ref)
         dps = ps64 - oracle.psnr(xh, xs)
@@ -139,6 +147,9 @@ def main():
     ap.add_argument("--warmup", type=int, default=10)
     ap.add_argument("--cpu-images", type=int, default=256, help="images in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency under load) leg")
+    ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--serve-qps", type=float, default=3000.0)
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -161,8 +172,10 @@ def main():
     phi, x, prm, params, x_d, y = make_inputs(ctx, P, torch)
     N = N1 * N2
     res = {}
-    for prec in ("bf16", "f32"):
+    for prec in ("bf16", "f32", "fp8"):
         net = ctx.prepare(N1, N2, M, params, prec=prec)
+        if prec == "fp8":
+            net.calibrate(calibration_y(ctx, P, torch, phi))
         net.reserve(BATCH)
         r = time_path(ctx, net, y, args.steps, args.warmup, torch, stage_timing=True)
         r["xhat_host"] = r["xhat"].cpu().numpy()
@@ -194,6 +207,8 @@ def main():
                    "global_batch": BATCH, "image": [N1, N2], "M": M, "parallelism": "single GPU"},
         "fp32": {"value": BATCH * args.steps / (f_ms * args.steps / 1e3), "ms_per_step": f_ms,
                  "stages_ms": f["stages"]},
+        "fp8": {"value": BATCH * args.steps / (res["fp8"]["total_ms"] / 1e3),
+                "ms_per_step": res["fp8"]["total_ms"] / args.steps, "stages_ms": res["fp8"]["stages"]},
         "speedup_bf16_vs_fp32": f_ms / ms_step,
         "latency_ms_per_batch": {"p50": float(np.percentile(b["per_step_ms"], 50)),
                                  "p99": float(np.percentile(b["per_step_ms"], 99)),
@@ -208,11 +223,16 @@ def main():
     }
     if not args.no_cpu:
         y_host = y.cpu().numpy().astype(np.float64)
-        cb, acc = cpu_baseline(phi, x, prm, y_host, res["bf16"]["xhat_host"], res["f32"]["xhat_host"],
-                               args.cpu_images)
+        cb, acc = cpu_baseline(phi, x, prm, y_host, {k: res[k]["xhat_host"] for k in res}, args.cpu_images)
         out["cpu_baseline"] = cb
         out["accuracy_vs_fp64_on_sample"] = acc
     ctx.close()
+    if not args.no_serve:
+        from paper_1701_03891_amd import serve
+        out["serving"] = serve.run_serving(n_req=args.serve_requests, qps=args.serve_qps, slots=2,
+                                           budget_gib=16.0, warmup=200)
+        out["serving"]["workload"] = ("Poisson arrivals, 1-32 images per request, 9 networks "
+                                      "(32/64/128 px x M/N 0.10/0.25/0.50), BF16, 2 streams, HIP graphs")
     print(json.dumps(out))
 
 

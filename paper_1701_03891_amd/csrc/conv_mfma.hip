@@ -85,12 +85,16 @@ template <> DSI_INLINE void load4f<bf16>(const bf16 *src, float *o) {
 // EPI_BIAS: out = ReLU?(oscale * acc + bias); bias per pixel [H][W][COUT] or per channel [COUT] (fp32)
 // EPI_MASK: out = acc * (mask > 0), mask in the output layout (backward through ReLU)
 // oscale dequantises FP8 products (weight scale x activation scale); 1 otherwise.
-template <typename T, int CIN, int COUT, int ROWS, int EPI, typename TO>
-__global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in, const T *__restrict__ wp,
-                                                       const float *__restrict__ bias, int bias_pp, int relu,
-                                                       const T *__restrict__ mask, TO *__restrict__ out,
-                                                       int H, int W, int tiles_w, int tiles_per_img, float oscale) {
-  constexpr int TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
+// A block has WAVES waves stacked vertically (WAVES * ROWS output rows x 32 columns).
+// The weight fragments of tap column v + 1 are loaded while tap column v computes.
+template <typename T, int CIN, int COUT, int ROWS, int WAVES, int EPI, typename TO>
+__global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restrict__ in, const T *__restrict__ wp,
+                                                              const float *__restrict__ bias, int bias_pp, int relu,
+                                                              const T *__restrict__ mask, TO *__restrict__ out,
+                                                              int H, int W, int tiles_w, int tiles_per_img,
+                                                              float oscale) {
+  constexpr int NT = 64 * WAVES;
+  constexpr int TH = WAVES * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
   constexpr int SC = slice_ch<T>();
   constexpr int CH16 = SC * (int)sizeof(T) / 16;  // 16-byte chunks per pixel per slice: bf16 2, fp32 4, fp8 4
   constexpr int FE = 16 * (CH16 / 2) / (int)sizeof(T);  // fragment elements per lane: 8, 8, 32
@@ -113,7 +117,7 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
   for (int cs = 0; cs < NCS; ++cs) {
     __syncthreads();  // previous slice fully consumed
     const T *src = in + (long)(img * NCS + cs) * H * W * SC;
-    for (int idx = tid; idx < LH * LW * CH16; idx += 256) {
+    for (int idx = tid; idx < LH * LW * CH16; idx += NT) {
       const int chunk = idx / (LH * LW), pix = idx - chunk * (LH * LW);
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
@@ -124,12 +128,18 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
     }
     __syncthreads();
     const T *wcs = wp + (long)cs * KT * KT * NCT * 64 * FE + lane * FE;
+    Frag8<T> wf[KT][NCT], wn[KT][NCT];
+#pragma unroll
+    for (int u = 0; u < KT; ++u)
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + (u * NCT + c) * 64 * FE);
     for (int v = 0; v < KT; ++v) {
-      Frag8<T> wf[KT][NCT];
+      if (v + 1 < KT) {
 #pragma unroll
-      for (int u = 0; u < KT; ++u)
+        for (int u = 0; u < KT; ++u)
 #pragma unroll
-        for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + ((v * KT + u) * NCT + c) * 64 * FE);
+          for (int c = 0; c < NCT; ++c) wn[u][c] = frag_load<T>(wcs + (((v + 1) * KT + u) * NCT + c) * 64 * FE);
+      }
       const unsigned char *lrow = lds + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + (px + v) * 16;
 #pragma unroll
       for (int rr = 0; rr < ROWS + 2 * RAD; ++rr) {
@@ -143,6 +153,10 @@ __global__ __launch_bounds__(256) void conv_mid_kernel(const T *__restrict__ in,
           }
         }
       }
+#pragma unroll
+      for (int u = 0; u < KT; ++u)
+#pragma unroll
+        for (int c = 0; c < NCT; ++c) wf[u][c] = wn[u][c];
     }
   }
 
@@ -381,10 +395,13 @@ hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, in
                     TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
   constexpr int ROWS = COUT == 32 ? 8 : 4;
+  // BF16 with 32 outputs: 8 waves (two per SIMD) on a 64 x 32 tile; its 74-row halo
+  // slice (99 KiB of LDS) fits one block per CU.  Wider types keep 4 waves.
+  constexpr int WAVES = (sizeof(T) == 2 && COUT == 32) ? 8 : 4;
   int tw, tpi;
-  tiles(H, W, 4 * ROWS, 32, tw, tpi);
-  conv_mid_kernel<T, CIN, COUT, ROWS, EPI, TO>
-      <<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
+  tiles(H, W, WAVES * ROWS, 32, tw, tpi);
+  conv_mid_kernel<T, CIN, COUT, ROWS, WAVES, EPI, TO>
+      <<<B * tpi, 64 * WAVES, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
   return hipGetLastError();
 }
 
