@@ -107,6 +107,38 @@ def time_path(ctx, net, y, steps, warmup, torch, stage_timing):
     return dict(total_ms=total_ms, wall_s=wall, per_step_ms=per, stages=stages, xhat=xh)
 
 
+def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=1e-3, pool=1024):
+    """Adam training of the network (Sec. 4: MSE loss, backpropagation) on a pool of
+    synthetic piecewise-smooth 64x64 images (a different seed from the benchmark
+    batch), BF16 compute with FP32 master weights, through dsi_train_step.
+    Updates `params` in place; returns the training statistics."""
+    import synth
+    dev = "cuda:0"
+    xs = synth.piecewise_smooth_images(pool, N1, N2, cfg_id=3, stream=11).reshape(pool, -1)
+    xd = torch.tensor(xs, dtype=torch.float32, device=dev)
+    yd = ctx.measure(torch.tensor(np.ascontiguousarray(phi), dtype=torch.float32, device=dev), xd)
+    net = ctx.prepare(N1, N2, M, params, prec="bf16")
+    net.reserve(batch, train=True)
+    opt = P.AdamState.zeros_like(params)
+    g = synth.rng(3, 12)
+    idx = [torch.tensor(g.choice(pool, size=batch, replace=False), device=dev) for _ in range(steps)]
+    losses = []
+    ev0, ev1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    ev0.record()
+    for s in range(steps):
+        loss = net.train_step(params, opt, yd[idx[s]].contiguous(), xd[idx[s]].contiguous(), lr=lr)
+        if s % 50 == 0 or s == steps - 1:
+            losses.append(loss)
+    ev1.record()
+    torch.cuda.synchronize()
+    ms = ev0.elapsed_time(ev1) / max(steps, 1)
+    net.free()
+    L = [float(v.item()) for v in losses]
+    return {"steps": steps, "batch": batch, "lr": lr, "ms_per_step": ms, "images_per_s": batch / (ms / 1e3),
+            "loss_first": L[0], "loss_last": L[-1], "precision": "bf16 compute, fp32 master weights"}
+
+
 def calibration_y(ctx, P, torch, phi, B=64):
     """Measurements of a separate seeded calibration batch (FP8 static activation scales)."""
     import synth
@@ -136,7 +168,10 @@ def cpu_baseline(phi, x, prm, y_host, xhs, n_img):
         rel = oracle.relerr(xh, ref)
         dps = ps64 - oracle.psnr(xh, xs)
         acc[name] = {"max_relerr_vs_fp64": float(rel.max()), "dpsnr_mean_db": float(dps.mean()),
-                     "dpsnr_max_abs_db": float(np.abs(dps).max())}
+                     "dpsnr_max_abs_db": float(np.abs(dps).max()),
+                     "psnr_mean_db": float(oracle.psnr(xh, xs).mean()),
+                     "success_rate": float(oracle.success(xh, xs).mean())}
+    acc["fp64"] = {"psnr_mean_db": float(ps64.mean()), "success_rate": float(oracle.success(ref, xs).mean())}
     return out, acc
 
 
@@ -148,6 +183,8 @@ def main():
     ap.add_argument("--cpu-images", type=int, default=256, help="images in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency under load) leg")
+    ap.add_argument("--train-steps", type=int, default=400,
+                    help="Adam steps on synthetic images before timing (0: He-init weights)")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--serve-qps", type=float, default=3000.0)
     ap.add_argument("--copy-mib", type=int, default=0,
@@ -171,6 +208,12 @@ def main():
         del src, dst
     phi, x, prm, params, x_d, y = make_inputs(ctx, P, torch)
     N = N1 * N2
+    train = None
+    if args.train_steps > 0:
+        train = train_network(ctx, P, torch, phi, params, args.train_steps)
+        # the oracle and every precision below use the trained FP32 parameters
+        prm.w = [w.cpu().numpy().astype(np.float64) for w in params.w]
+        prm.b = [b.cpu().numpy().astype(np.float64) for b in params.b]
     res = {}
     for prec in ("bf16", "f32", "fp8"):
         net = ctx.prepare(N1, N2, M, params, prec=prec)
@@ -203,6 +246,8 @@ def main():
         "dtype": "bf16",
         "data": "synthetic",
         "config": {"workload": "DeepInverse recovery, 64x64 images, M=1024 (M/N=0.25), batch 256, "
+                               "1->64->32->1 conv 11x11, weights trained on synthetic images"
+                               if train else "DeepInverse recovery, 64x64 images, M=1024 (M/N=0.25), batch 256, "
                                "1->64->32->1 conv 11x11, He-init",
                    "global_batch": BATCH, "image": [N1, N2], "M": M, "parallelism": "single GPU"},
         "fp32": {"value": BATCH * args.steps / (f_ms * args.steps / 1e3), "ms_per_step": f_ms,
@@ -220,6 +265,7 @@ def main():
                      "frac": achieved / PEAK_BF16_TFLOPS, "traffic": conv2_traffic(),
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"},
         "cpu_baseline": None,
+        "training": train,
     }
     if not args.no_cpu:
         y_host = y.cpu().numpy().astype(np.float64)

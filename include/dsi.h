@@ -75,6 +75,8 @@ typedef struct {
                           0: one bias per output channel [Cout] */
   int relu_last;       /* 1: ReLU after the last layer as well (Sec. 4 applies ReLU in every
                           layer); 0: linear last layer, so signed signals stay representable */
+  int fc_trainable;    /* 1: the fully connected layer W_fc is learned too (Sec. 4 notes that
+                          it could be); 0: it stays fixed at its given value (Phi^T in the paper) */
 } dsi_net_desc;
 
 /* Parameters Omega (Sec. 4), FP32.  Device pointers.  For dsi_net_prepare and
@@ -86,7 +88,8 @@ typedef struct {
   float *b[DSI_MAX_LAYERS];     /* [Cout][n1][n2] if bias_per_pixel, else [Cout] */
 } dsi_params;
 
-/* Gradients, same shapes as dsi_params, FP32 device pointers (w_fc unused). */
+/* Gradients, same shapes as dsi_params, FP32 device pointers (w_fc written only
+ * when the net's fc_trainable is set; it may be NULL otherwise). */
 typedef dsi_params dsi_grads;
 
 /* Adam state (Kingma & Ba): first and second moments with the shapes of
@@ -96,6 +99,7 @@ typedef struct {
   float *m_b[DSI_MAX_LAYERS], *v_b[DSI_MAX_LAYERS];
   float beta1, beta2, eps;      /* 0.9, 0.999, 1e-8 */
   long step;                    /* completed steps; dsi_train_step increments it (host field) */
+  float *m_fc, *v_fc;           /* [N][M] moments of W_fc (used when fc_trainable) */
 } dsi_adam;
 
 /* ------------------------------------------------------------ lifetime */
@@ -113,6 +117,13 @@ const char *dsi_version(void);
  * phi [M][N], x [B][N], y [B][M].  B = 0 is an empty batch (no-op). */
 dsi_status dsi_measure(dsi_ctx *ctx, const float *phi, const float *x, float *y,
                        int B, int M, int N, void *stream);
+
+/* Noisy measurements (Sec. 5, Table 3): y_b = Phi x_b + s_b e_b, with the
+ * noise draw e [B][M] (caller-supplied, device) scaled per vector so that
+ * ||Phi x_b||^2 / ||s_b e_b||^2 = 10^(snr_db/10).  Other arguments as
+ * dsi_measure. */
+dsi_status dsi_measure_noisy(dsi_ctx *ctx, const float *phi, const float *x, const float *e,
+                             double snr_db, float *y, int B, int M, int N, void *stream);
 
 /* ------------------------------------------- Sec. 4: the recovery network */
 /* Validate `desc`, copy and pack `params` into the precision `prec`, and
@@ -186,8 +197,9 @@ dsi_status dsi_loss_grad(dsi_ctx *ctx, dsi_net *net, const float *y, const float
                          const dsi_grads *grads, float *gy, double *loss_dev, void *stream);
 /* One training step on a batch (Sec. 4): forward in the net's precision, loss
  * L = (1/B) sum_b ||xhat_b - x_b||^2 (accumulated in FP64), backward, Adam
- * update (lr) of the FP32 master parameters `params` (w and b; w_fc stays
- * fixed, as in the paper), and a re-pack of the net from them.  y [B][M],
+ * update (lr) of the FP32 master parameters `params` (w and b, and w_fc when
+ * the net's fc_trainable is set; otherwise w_fc stays fixed, as in the
+ * paper's experiments), and a re-pack of the net from them.  y [B][M],
  * x [B][n1][n2].  loss_dev (nullable) is a device double that receives L.
  * opt->step is incremented on the host. */
 dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, dsi_adam *opt,

@@ -57,6 +57,7 @@ def lib():
         sig = {
             "orc_measure": (None, [P, P, P, i, i, i]),
             "orc_proxy": (None, [P, P, P, i, i, i]),
+            "orc_add_noise": (None, [P, P, i, i, d]),
             "orc_conv_layer": (None, [P, i, i, i, P, i, i, P, i, i, P, P]),
             "orc_acts_per_image": (l_, [P]),
             "orc_forward": (None, [P, P, P, P, P, i, P, P]),
@@ -166,6 +167,14 @@ def measure(phi, x):
     return y
 
 
+def add_noise(y, e, snr_db):
+    """y + s e per row with ||y||^2 / ||s e||^2 = 10^(snr_db/10) (Sec. 5, Table 3: noisy measurements)."""
+    y, e = _c(y).copy(), _c(e)
+    B, M = y.shape
+    lib().orc_add_noise(_p(y), _p(e), B, M, float(snr_db))
+    return y
+
+
 def proxy(wfc, y):
     """Signal proxy x~ = Phi^T y by the fixed fully connected layer (Sec. 4). wfc [N][M]."""
     wfc, y = _c(wfc), _c(y)
@@ -270,7 +279,7 @@ def backward(net: Net, wfc, w, b, y, x, want_gy=False, want_gwfc=False) -> Grads
     return Grads(L, gw, gb, gy, gwfc)
 
 
-def backward_acts(net: Net, wfc, w, y, acts, g_out, want_gy=False) -> Grads:
+def backward_acts(net: Net, wfc, w, y, acts, g_out, want_gy=False, want_gwfc=False) -> Grads:
     """Backpropagation (Sec. 4) from GIVEN activations: acts[b] = [a_0, ..., a_L]
     (each [C_l][n1][n2]), g_out = dL/dxhat [B][N].  ReLU masks come from the
     given post-activations, so a network whose forward pass ran elsewhere
@@ -283,10 +292,12 @@ def backward_acts(net: Net, wfc, w, y, acts, g_out, want_gy=False) -> Grads:
     gw = [np.empty_like(a) for a in ws]
     gb = [np.empty(net.full_bias_shape(l) if net.bias_full else (net.C[l + 1],)) for l in range(net.L)]
     gy = np.empty_like(y) if want_gy else None
+    gwfc = np.empty_like(wfc) if want_gwfc else None
     cn = net._c()
     lib().orc_backward_acts(ctypes.byref(cn), _p(wfc), _ptr_array(ws), _p(y), _p(flat), _p(g_out), B,
-                            _ptr_array(gw), _ptr_array(gb), _p(gy) if gy is not None else None, None)
-    return Grads(float("nan"), gw, gb, gy, None)
+                            _ptr_array(gw), _ptr_array(gb), _p(gy) if gy is not None else None,
+                            _p(gwfc) if gwfc is not None else None)
+    return Grads(float("nan"), gw, gb, gy, gwfc)
 
 
 def adam(theta, g, m, v, t, lr=1e-3, beta1=0.9, beta2=0.999, eps=1e-8):

@@ -26,6 +26,20 @@ void orc_measure(const double *phi, const double *x, double *y, int B, int M, in
     }
 }
 
+/* Noisy measurements (Sec. 5, Table 3): y_b <- y_b + s_b e_b with s_b chosen so
+ * that ||y_b||^2 / ||s_b e_b||^2 = 10^(snr_db / 10).  e is the noise draw. */
+void orc_add_noise(double *y, const double *e, int B, int M, double snr_db) {
+  for (int b = 0; b < B; ++b) {
+    double ny = 0.0, ne = 0.0;
+    for (int m = 0; m < M; ++m) {
+      ny += y[(long)b * M + m] * y[(long)b * M + m];
+      ne += e[(long)b * M + m] * e[(long)b * M + m];
+    }
+    const double s = ne > 0.0 ? sqrt(ny / ne) * pow(10.0, -snr_db / 20.0) : 0.0;
+    for (int m = 0; m < M; ++m) y[(long)b * M + m] += s * e[(long)b * M + m];
+  }
+}
+
 /* ------------------------------------------------------------------ Sec. 4 */
 void orc_proxy(const double *wfc, const double *y, double *xt, int B, int M, int N) {
   /* fully connected layer with weights Phi^T: xt = Phi^T y */

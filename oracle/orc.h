@@ -50,6 +50,10 @@ typedef struct {
 /* y[b][m] = sum_n phi[m][n] x[b][n]                                    (Sec. 1) */
 void orc_measure(const double *phi, const double *x, double *y, int B, int M, int N);
 
+/* Noisy measurements (Sec. 5, Table 3): y_b += s_b e_b, s_b such that
+ * ||y_b||^2 / ||s_b e_b||^2 = 10^(snr_db/10).  e [B][M] is the noise draw. */
+void orc_add_noise(double *y, const double *e, int B, int M, double snr_db);
+
 /* xt[b][p] = sum_m wfc[p][m] y[b][m]; wfc = Phi^T, shape [N][M]         (Sec. 4) */
 void orc_proxy(const double *wfc, const double *y, double *xt, int B, int M, int N);
 

@@ -70,12 +70,15 @@ class NetParams:
         return p
 
     @staticmethod
-    def grads_like(params: "NetParams") -> "NetParams":
+    def grads_like(params: "NetParams", with_fc: bool = False) -> "NetParams":
         torch = _torch()
-        return NetParams(None, [torch.zeros_like(w) for w in params.w], [torch.zeros_like(b) for b in params.b])
+        return NetParams(torch.zeros_like(params.w_fc) if with_fc else None,
+                         [torch.zeros_like(w) for w in params.w], [torch.zeros_like(b) for b in params.b])
 
     def grads_to_c(self) -> Params:
         p = Params()
+        if self.w_fc is not None:
+            p.w_fc = _ptr(_f32(self.w_fc, "gw_fc")).value
         for l, (w, b) in enumerate(zip(self.w, self.b)):
             p.w[l] = _ptr(_f32(w, f"gw[{l}]")).value
             p.b[l] = _ptr(_f32(b, f"gb[{l}]")).value
@@ -93,12 +96,18 @@ class AdamState:
     eps: float = 1e-8
     c: Adam | None = None
 
+    m_fc: object = None
+    v_fc: object = None
+
     @staticmethod
-    def zeros_like(params: NetParams, beta1=0.9, beta2=0.999, eps=1e-8) -> "AdamState":
+    def zeros_like(params: NetParams, beta1=0.9, beta2=0.999, eps=1e-8, with_fc=False) -> "AdamState":
         torch = _torch()
         z = lambda ts: [torch.zeros_like(t) for t in ts]  # noqa: E731
         s = AdamState(z(params.w), z(params.w), z(params.b), z(params.b), beta1, beta2, eps)
         c = Adam()
+        if with_fc:
+            s.m_fc, s.v_fc = torch.zeros_like(params.w_fc), torch.zeros_like(params.w_fc)
+            c.m_fc, c.v_fc = s.m_fc.data_ptr(), s.v_fc.data_ptr()
         for l in range(len(params.w)):
             c.m_w[l] = s.m_w[l].data_ptr()
             c.v_w[l] = s.v_w[l].data_ptr()
@@ -113,8 +122,10 @@ class AdamState:
         return int(self.c.step)
 
 
-def make_desc(n1, n2, M, C=PAPER_C, k=PAPER_K, bias_per_pixel=True, relu_last=False) -> NetDesc:
+def make_desc(n1, n2, M, C=PAPER_C, k=PAPER_K, bias_per_pixel=True, relu_last=False,
+              fc_trainable=False) -> NetDesc:
     d = NetDesc()
+    d.fc_trainable = int(fc_trainable)
     d.n1, d.n2, d.M, d.L = n1, n2, M, len(k)
     for q, c in enumerate(C):
         d.C[q] = c
@@ -155,9 +166,20 @@ class Context:
                          _stream(self.device))
         return y
 
+    def measure_noisy(self, phi, x, e, snr_db, y=None):
+        """y = Phi x + s e with per-vector SNR snr_db (Sec. 5, Table 3). e [B][M] is the noise draw."""
+        torch = _torch()
+        M, N = phi.shape
+        B = x.shape[0]
+        if y is None:
+            y = torch.empty((B, M), dtype=torch.float32, device=x.device)
+        _lib.dsi_measure_noisy(self.h, _ptr(_f32(phi, "phi")), _ptr(_f32(x, "x")), _ptr(_f32(e, "e")), snr_db,
+                               _ptr(y), B, M, N, _stream(self.device))
+        return y
+
     def prepare(self, n1, n2, M, params: NetParams, prec="bf16", C=PAPER_C, k=PAPER_K,
-                bias_per_pixel=True, relu_last=False) -> "Net":
-        desc = make_desc(n1, n2, M, C, k, bias_per_pixel, relu_last)
+                bias_per_pixel=True, relu_last=False, fc_trainable=False) -> "Net":
+        desc = make_desc(n1, n2, M, C, k, bias_per_pixel, relu_last, fc_trainable)
         p = PREC[prec] if isinstance(prec, str) else int(prec)
         h = _lib.dsi_net_prepare(self.h, desc, params.to_c(), p, _stream(self.device))
         return Net(self, h, desc, p)
@@ -238,7 +260,7 @@ class Net:
     def backward(self, gxhat, saved, params_like: NetParams, want_gy=False):
         torch = _torch()
         B = gxhat.shape[0]
-        g = NetParams.grads_like(params_like)
+        g = NetParams.grads_like(params_like, with_fc=bool(self.desc.fc_trainable))
         gy = torch.empty((B, self.M), dtype=torch.float32, device=gxhat.device) if want_gy else None
         _lib.dsi_backward(self.ctx.h, self.h, _ptr(_f32(gxhat.contiguous(), "gxhat")), _ptr(saved),
                           saved.numel(), B, g.grads_to_c(), _ptr(gy), _stream(self.ctx.device))
@@ -247,7 +269,7 @@ class Net:
     def loss_grad(self, y, x, params_like: NetParams, want_gy=False):
         torch = _torch()
         B = y.shape[0]
-        g = NetParams.grads_like(params_like)
+        g = NetParams.grads_like(params_like, with_fc=bool(self.desc.fc_trainable))
         gy = torch.empty((B, self.M), dtype=torch.float32, device=y.device) if want_gy else None
         loss = torch.empty((), dtype=torch.float64, device=y.device)
         _lib.dsi_loss_grad(self.ctx.h, self.h, _ptr(_f32(y, "y")), _ptr(_f32(x, "x")), B, g.grads_to_c(),

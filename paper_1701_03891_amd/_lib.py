@@ -28,7 +28,7 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_net_info", "dsi_workspace_size", "dsi_reserve", "dsi_recover",
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
            "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation", "dsi_net_calibrate",
-           "dsi_net_get_scales"]
+           "dsi_net_get_scales", "dsi_measure_noisy"]
 
 
 class DsiError(RuntimeError):
@@ -41,7 +41,8 @@ class DsiError(RuntimeError):
 class NetDesc(ctypes.Structure):
     _fields_ = [("n1", ctypes.c_int), ("n2", ctypes.c_int), ("M", ctypes.c_int), ("L", ctypes.c_int),
                 ("C", ctypes.c_int * (MAX_LAYERS + 1)), ("k", ctypes.c_int * MAX_LAYERS),
-                ("bias_per_pixel", ctypes.c_int), ("relu_last", ctypes.c_int)]
+                ("bias_per_pixel", ctypes.c_int), ("relu_last", ctypes.c_int),
+                ("fc_trainable", ctypes.c_int)]
 
 
 class Params(ctypes.Structure):
@@ -53,7 +54,7 @@ class Adam(ctypes.Structure):
     _fields_ = [("m_w", ctypes.c_void_p * MAX_LAYERS), ("v_w", ctypes.c_void_p * MAX_LAYERS),
                 ("m_b", ctypes.c_void_p * MAX_LAYERS), ("v_b", ctypes.c_void_p * MAX_LAYERS),
                 ("beta1", ctypes.c_float), ("beta2", ctypes.c_float), ("eps", ctypes.c_float),
-                ("step", ctypes.c_long)]
+                ("step", ctypes.c_long), ("m_fc", ctypes.c_void_p), ("v_fc", ctypes.c_void_p)]
 
 
 _lib = None
@@ -76,6 +77,7 @@ def lib() -> ctypes.CDLL:
         "dsi_last_error": (ctypes.c_char_p, []),
         "dsi_version": (ctypes.c_char_p, []),
         "dsi_measure": (st, [P, P, P, P, i, i, i, P]),
+        "dsi_measure_noisy": (st, [P, P, P, P, ctypes.c_double, P, i, i, i, P]),
         "dsi_net_prepare": (st, [P, ctypes.POINTER(NetDesc), ctypes.POINTER(Params), i, ctypes.POINTER(P), P]),
         "dsi_net_update": (st, [P, P, ctypes.POINTER(Params), P]),
         "dsi_net_set_act_scales": (st, [P, ctypes.POINTER(ctypes.c_float), i]),
@@ -213,3 +215,7 @@ def dsi_net_get_scales(net, n=6):
     arr = (ctypes.c_float * n)()
     call("dsi_net_get_scales", net, arr, n)
     return list(arr)
+
+
+def dsi_measure_noisy(ctx, phi, x, e, snr_db, y, B, M, N, stream):
+    call("dsi_measure_noisy", ctx, phi, x, e, float(snr_db), y, B, M, N, stream)

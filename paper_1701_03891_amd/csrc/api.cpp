@@ -106,7 +106,7 @@ struct dsi_net {
   void *b[DSI_MAX_LAYERS] = {};
   // paper path
   void *wp1 = nullptr, *wp2 = nullptr, *wp3 = nullptr;  // packed (compute precision)
-  float *bp[3] = {};                                     // fp32 biases, per-pixel ones as [H][W][C]
+  float *bp[3] = {};                                     // fp32 biases (layout of dsi_params)
   float *w32[3] = {};                                    // OIHW fp32 copies (backward)
   float *b32[3] = {};                                    // fp32 biases in caller layout (backward)
   void *wp3f = nullptr, *wp2f = nullptr, *wp1f = nullptr;  // packed data-gradient operators
@@ -148,7 +148,7 @@ long bcount(const dsi_net_desc &d, int l) { return d.bias_per_pixel ? (long)d.C[
 
 // --------------------------------------------------------- workspace layout
 struct Layout {
-  size_t ypad = 0, xt = 0, act[DSI_MAX_LAYERS + 1] = {}, xh64 = 0, y64 = 0, end = 0;
+  size_t ypad = 0, xt = 0, act[DSI_MAX_LAYERS + 1] = {}, xh64 = 0, y64 = 0, ykeep = SIZE_MAX, end = 0;
 };
 
 // Recovery workspace (train = 0) or training state (train = 1) for B images.
@@ -177,6 +177,10 @@ Layout layout(const dsi_net &n, int B, int train) {
     const bool last = l == n.d.L;
     if (last && !train && !(n.prec == DSI_F64)) { L.act[l] = SIZE_MAX; continue; }  // written to xhat directly
     off += rnd((size_t)B * n.d.C[l] * N * (last && n.path == PATH_PAPER ? 4 : es));
+  }
+  if (train && n.d.fc_trainable) {  // y is kept for the gradient of W_fc
+    L.ykeep = off;
+    off += rnd((size_t)B * n.d.M * 4);
   }
   L.end = off;
   return L;
@@ -260,20 +264,21 @@ dsi_status pack_params_fp8(dsi_net *n, const dsi_params *p, hipStream_t s) {
   HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, 1, s));
   for (int l = 0; l < 3; ++l) {
     const int C = d.C[l + 1];
-    if (d.bias_per_pixel && C > 1) HIPCHK(dsi::pack_bias_hwc(p->b[l], n->bp[l], C, N, s));
-    else HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    (void)C;  // per-pixel biases stay planar [C][H][W]: the epilogues read them coalesced
+    HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
   }
   return DSI_OK;
 }
 
-// copy/convert parameters into the net's own storage (enqueued on s)
-dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
+// copy/convert parameters into the net's own storage (enqueued on s); with_fc = false
+// leaves the FC layer as it is (a training step whose W_fc is fixed)
+dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with_fc = true) {
   const dsi_net_desc &d = n->d;
   const int N = n->N, HW = N;
   const int pr = n->prec == DSI_BF16 ? 1 : 0;
   if (n->prec == DSI_F64) {
     // FP64: W_fc [N][M] as double (unpadded), OIHW weights and biases as double
-    HIPCHK(dsi::cast_f32_f64(p->w_fc, (double *)n->wfc, (long)N * d.M, s));
+    if (with_fc) HIPCHK(dsi::cast_f32_f64(p->w_fc, (double *)n->wfc, (long)N * d.M, s));
     for (int l = 0; l < d.L; ++l) {
       HIPCHK(dsi::cast_f32_f64(p->w[l], (double *)n->w[l], wcount(d, l), s));
       HIPCHK(dsi::cast_f32_f64(p->b[l], (double *)n->b[l], bcount(d, l), s));
@@ -281,10 +286,12 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
     return DSI_OK;
   }
   if (n->prec == DSI_FP8_E4M3) return pack_params_fp8(n, p, s);
-  HIPCHK(dsi::pack_fc(p->w_fc, n->wfc, N, d.M, n->Mpad, pr, s));
-  if (n->wfcT) {
-    (void)hipFree(n->wfcT);
-    n->wfcT = nullptr;
+  if (with_fc) {
+    HIPCHK(dsi::pack_fc(p->w_fc, n->wfc, N, d.M, n->Mpad, pr, s));
+    if (n->wfcT) {
+      (void)hipFree(n->wfcT);
+      n->wfcT = nullptr;
+    }
   }
   if (n->path == PATH_GENERIC) {
     for (int l = 0; l < d.L; ++l) {
@@ -302,8 +309,8 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s) {
   HIPCHK(dsi::pack_last(p->w[0], n->wp1f, 64, 1, pr, s));
   for (int l = 0; l < 3; ++l) {
     const int C = d.C[l + 1];
-    if (d.bias_per_pixel && C > 1) HIPCHK(dsi::pack_bias_hwc(p->b[l], n->bp[l], C, HW, s));
-    else HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    (void)C;  // per-pixel biases stay planar [C][H][W]: the epilogues read them coalesced
+    HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(n->w32[l], p->w[l], wcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
     HIPCHK(hipMemcpyAsync(n->b32[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
   }
@@ -317,6 +324,8 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
   const dsi_net_desc &d = n->d;
   const int N = n->N, H = d.n1, W = d.n2, M = d.M;
   (void)ctx;
+  if (L.ykeep != SIZE_MAX)
+    HIPCHK(hipMemcpyAsync(at<float>(base, L.ykeep), y, (size_t)B * M * 4, hipMemcpyDeviceToDevice, s));
   if (n->prec == DSI_F64) {
     double *y64 = at<double>(base, L.ypad);
     double *xt = at<double>(base, L.xt);
@@ -437,12 +446,13 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
       HIPCHK(dsi::cast_f64_f32(wtmp, g->w[l], wcount(d, l), s));
       HIPCHK((dsi::bias_grad<double, double, double>(gz, vg, B, d.bias_per_pixel, wtmp, s)));
       HIPCHK(dsi::cast_f64_f32(wtmp, g->b[l], bcount(d, l), s));
-      if (l == 0 && !gy) break;
+      if (l == 0 && !gy && !(d.fc_trainable && g->w_fc)) break;
       double *go = gbuf[l & 1];
       HIPCHK((dsi::conv_dgrad_direct<double, double, double, double, double>(
           gz, vg, (const double *)n->w[l], l > 0 ? in : nullptr, vi, go, vi, B, d.k[l], s)));
       gz = go;
     }
+    if (d.fc_trainable && g->w_fc) HIPCHK(dsi::fc_wgrad_f64(gz, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, s));
     if (gy) {
       // dy[b][m] = sum_p W_fc[p][m] g_xt[b][p]: transpose W_fc into wtmp as [M][N]
       double *wT = wtmp;
@@ -479,7 +489,7 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
       HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>(gz, vg, (const float *)in, vi, B, d.k[l], g->w[l], s)));
     }
     HIPCHK((dsi::bias_grad<float, float, float>(gz, vg, B, d.bias_per_pixel, g->b[l], s)));
-    if (l == 0 && !gy) break;
+    if (l == 0 && !gy && !(d.fc_trainable && g->w_fc)) break;
     float *go = gbuf[l & 1];
     ActView vo{d.C[l], H, W, 0};
     if (paper && n->prec == DSI_BF16 && l > 0) {
@@ -491,6 +501,7 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
     }
     gz = go;
   }
+  if (d.fc_trainable && g->w_fc) HIPCHK(dsi::fc_wgrad_f32(gz, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, s));
   if (gy) {
     // dy = g_xt W_fc: X = g_xt [B][N], W = W_fc^T [M][N] (fp32, built once)
     if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
@@ -540,9 +551,14 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
     HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>((const float *)g1, v64, (const float *)xt, v1, B, 11, g->w[0], s)));
   }
   HIPCHK((dsi::bias_grad<T, float, float>(g1, v64, B, bpp, g->b[0], s)));
-  if (gy) {
-    // dL/dx~ = dgrad of layer 1, then dy = g_xt W_fc
+  const bool want_fc = d.fc_trainable && g->w_fc;
+  if (gy || want_fc) {
+    // dL/dx~ = dgrad of layer 1
     HIPCHK((dsi::conv_last<T, 64>(g1, (const T *)n->wp1f, nullptr, 0, 0, gxt, B, H, W, s)));
+  }
+  if (want_fc) HIPCHK(dsi::fc_wgrad_f32(gxt, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, s));
+  if (gy) {
+    // dy = g_xt W_fc
     if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
     HIPCHK(dsi::gemm_nt_f32(gxt, N, n->wfcT, N, gy, M, B, M, N, N % 16 == 0, s));
   }
@@ -615,6 +631,16 @@ dsi_status dsi_measure(dsi_ctx *ctx, const float *phi, const float *x, float *y,
   if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
   const bool vec = N % 16 == 0;
   HIPCHK(dsi::gemm_nt_f32(x, N, phi, N, y, M, B, M, N, vec, (hipStream_t)stream));
+  return DSI_OK;
+}
+
+dsi_status dsi_measure_noisy(dsi_ctx *ctx, const float *phi, const float *x, const float *e, double snr_db,
+                             float *y, int B, int M, int N, void *stream) {
+  if (!e && B > 0) return fail(DSI_E_NULL, "e must be non-NULL");
+  if (!std::isfinite(snr_db)) return fail(DSI_E_SHAPE, "snr_db must be finite");
+  dsi_status st = dsi_measure(ctx, phi, x, y, B, M, N, stream);
+  if (st != DSI_OK || B == 0) return st;
+  HIPCHK(dsi::add_noise(y, e, B, M, snr_db, (hipStream_t)stream));
   return DSI_OK;
 }
 
@@ -803,6 +829,7 @@ dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, f
 namespace {
 dsi_status check_grads(const dsi_net *net, const dsi_grads *g) {
   if (!g) return fail(DSI_E_NULL, "grads is NULL");
+  if (net->d.fc_trainable && !g->w_fc) return fail(DSI_E_NULL, "grads->w_fc is NULL for a trainable FC layer");
   for (int l = 0; l < net->d.L; ++l) {
     if (!g->w[l] || !g->b[l]) return fail(DSI_E_NULL, "grads of layer %d are NULL", l);
     if (!aligned16(g->w[l]) || !aligned16(g->b[l])) return fail(DSI_E_ALIGN, "grads of layer %d not aligned", l);
@@ -991,6 +1018,10 @@ dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, 
   const size_t scratch = backward_scratch_bytes(*net, B);
   size_t gbytes = 0;
   for (int l = 0; l < d.L; ++l) gbytes += rnd(wcount(d, l) * 4) + rnd(bcount(d, l) * 4);
+  if (d.fc_trainable) {
+    if (!opt->m_fc || !opt->v_fc) return fail(DSI_E_NULL, "Adam state of W_fc is NULL for a trainable FC layer");
+    gbytes += rnd((size_t)net->N * d.M * 4);
+  }
   if ((st = ensure_ws(ctx, L.end + scratch + gbytes)) != DSI_OK) return st;
   dsi_grads g{};
   size_t off = L.end + scratch;
@@ -998,6 +1029,7 @@ dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, 
     g.w[l] = at<float>(ctx->ws, off); off += rnd(wcount(d, l) * 4);
     g.b[l] = at<float>(ctx->ws, off); off += rnd(bcount(d, l) * 4);
   }
+  if (d.fc_trainable) g.w_fc = at<float>(ctx->ws, off);
   if ((st = loss_grad_impl(ctx, net, y, x, B, &g, nullptr, loss_dev, s)) != DSI_OK) return st;
   const long t = opt->step + 1;
   const float c1 = (float)(1.0 - std::pow((double)opt->beta1, (double)t));
@@ -1006,8 +1038,11 @@ dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, 
     HIPCHK(dsi::adam_f32(params->w[l], g.w[l], opt->m_w[l], opt->v_w[l], wcount(d, l), lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
     HIPCHK(dsi::adam_f32(params->b[l], g.b[l], opt->m_b[l], opt->v_b[l], bcount(d, l), lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
   }
+  if (d.fc_trainable)
+    HIPCHK(dsi::adam_f32(params->w_fc, g.w_fc, opt->m_fc, opt->v_fc, (long)net->N * d.M, lr, opt->beta1, opt->beta2,
+                         opt->eps, c1, c2, s));
   opt->step = t;
-  return pack_params(net, params, s);
+  return pack_params(net, params, s, d.fc_trainable != 0);
 }
 
 }  // extern "C"

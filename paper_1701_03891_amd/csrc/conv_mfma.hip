@@ -82,7 +82,7 @@ template <> DSI_INLINE void load4f<bf16>(const bf16 *src, float *o) {
 // in   [B][CIN/SC][H][W][SC]  (T; SC = 16 channels per slice, 64 for FP8)
 // wp   [CIN/SC][11 v][11 u][COUT/32][64 lanes][FE]  (T; FE = 8, 32 for FP8): lane l holds
 //      W[co = ct*32 + l%32][ci = cs*SC + (l/32)*FE + e][u][v]
-// EPI_BIAS: out = ReLU?(oscale * acc + bias); bias per pixel [H][W][COUT] or per channel [COUT] (fp32)
+// EPI_BIAS: out = ReLU?(oscale * acc + bias); bias per pixel [COUT][H][W] or per channel [COUT] (fp32)
 // EPI_MASK: out = acc * (mask > 0), mask in the output layout (backward through ReLU)
 // oscale dequantises FP8 products (weight scale x activation scale); 1 otherwise.
 // A block has WAVES waves stacked vertically (WAVES * ROWS output rows x 32 columns).
@@ -177,7 +177,12 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
         for (int e = 0; e < 4; ++e) vals[e] = acc[i][c][4 * q + e] * oscale;
         if constexpr (EPI == EPI_BIAS) {
           float bv[4];
-          load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
+          if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bv[e] = bias[((long)(co0 + e) * H + gi) * W + gj];
+          } else {
+            load4f<float>(bias + co0, bv);
+          }
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             vals[e] += bv[e];
@@ -225,29 +230,41 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   }
   __syncthreads();
 
-  Frag8<T> wf[KT][NCT];
+  // all ROWS x NCT accumulators live; filter rows u outermost, so each k-step issues
+  // ROWS * NCT independent MFMAs and the next row's weight fragments load meanwhile
+  f32x16 acc[ROWS][NCT];
 #pragma unroll
-  for (int u = 0; u < KT; ++u)
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wp + ((u * NCT + c) * 64 + lane) * 8);
-
-  const int gj = bj0 + px;
-  for (int ri = 0; ri < ROWS; ++ri) {
-    const int lr = wave * ROWS + ri;
-    f32x16 acc[NCT];
+  for (int ri = 0; ri < ROWS; ++ri)
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+      for (int r = 0; r < 16; ++r) acc[ri][c][r] = 0.0f;
+  Frag8<T> wf[NCT], wn[NCT];
 #pragma unroll
-    for (int u = 0; u < KT; ++u) {
+  for (int c = 0; c < NCT; ++c) wf[c] = frag_load<T>(wp + (c * 64 + lane) * 8);
+#pragma unroll
+  for (int u = 0; u < KT; ++u) {
+    if (u + 1 < KT) {
+#pragma unroll
+      for (int c = 0; c < NCT; ++c) wn[c] = frag_load<T>(wp + (((u + 1) * NCT + c) * 64 + lane) * 8);
+    }
+#pragma unroll
+    for (int ri = 0; ri < ROWS; ++ri) {
       // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e (unaligned)
       Frag8<T> xf;
-      __builtin_memcpy(&xf, tile + (lr + u) * LWA + px + 8 * h, sizeof(xf));
+      __builtin_memcpy(&xf, tile + (wave * ROWS + ri + u) * LWA + px + 8 * h, sizeof(xf));
       if (h) xf = frag_keep_first<T, 3>(xf);  // taps v >= 11 are padding: keep them finite-free
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) wf[u][c].mma(xf, acc[c]);
+      for (int c = 0; c < NCT; ++c) wf[c].mma(xf, acc[ri][c]);
     }
+#pragma unroll
+    for (int c = 0; c < NCT; ++c) wf[c] = wn[c];
+  }
+
+  const int gj = bj0 + px;
+#pragma unroll
+  for (int ri = 0; ri < ROWS; ++ri) {
+    const int lr = wave * ROWS + ri;
     const int gi = bi0 + lr;
     if (gi >= H || gj >= W) continue;
 #pragma unroll
@@ -258,10 +275,15 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         const long o = ((((long)img * (COUT / OSC) + co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC;
         float vals[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vals[e] = acc[c][4 * q + e];
+        for (int e = 0; e < 4; ++e) vals[e] = acc[ri][c][4 * q + e];
         if constexpr (EPI == EPI_BIAS) {
           float bv[4];
-          load4f<float>(bias_pp ? bias + ((long)gi * W + gj) * COUT + co0 : bias + co0, bv);
+          if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
+#pragma unroll
+            for (int e = 0; e < 4; ++e) bv[e] = bias[((long)(co0 + e) * H + gi) * W + gj];
+          } else {
+            load4f<float>(bias + co0, bv);
+          }
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             vals[e] += bv[e];
@@ -311,7 +333,9 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
   for (int idx = tid; idx < KT * KT * CIN; idx += 256) wl[idx] = wt[idx];
-  f32x4 acc = {0.0f, 0.0f, 0.0f, 0.0f};
+  f32x4 acc[4];
+#pragma unroll
+  for (int d = 0; d < 4; ++d) acc[d] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int pass = 0; pass < NPASS; ++pass) {
     __syncthreads();
     // stage 16-byte units: unit q of pixel covers channels pass*CHL + q*EPU .. +EPU
@@ -326,31 +350,42 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
       *reinterpret_cast<i32x4 *>(lds + (row * 4 + q) * UNIT_PLANE + col * 16) = val;
     }
     __syncthreads();
-    for (int v = 0; v < KT; ++v) {
-      const unsigned char *arow = lds + g * UNIT_PLANE + (wave * 16 + n + v) * 16;
-      const T *wv = wl + v * KT * CIN + pass * CHL + g * EPU;
+    // four tap columns at a time: four independent accumulator chains per row step
+    for (int v0 = 0; v0 < KT; v0 += 4) {
+      // Band operand B_r[n] = W[u = r - n][v] (zero outside 0..10).  Lane n at row r needs
+      // what lane n-1 held at row r-1, so B_r is B_{r-1} shifted by one lane within each
+      // 16-lane row (DPP row_shr:1, zero into lane 0), with lane 0 taking W[u = r].
+      i32x4 band[4];
+#pragma unroll
+      for (int d = 0; d < 4; ++d) band[d] = i32x4{0, 0, 0, 0};
 #pragma unroll
       for (int r = 0; r < LH; ++r) {
-        Frag8<T> a, b;
-        if constexpr (sizeof(T) == 2) {
-          a.v = *reinterpret_cast<const bf16x8 *>(arow + r * 4 * UNIT_PLANE);
-        } else {
-          a.lo = *reinterpret_cast<const f32x4 *>(arow + r * 4 * UNIT_PLANE);
+#pragma unroll
+        for (int d = 0; d < 4; ++d) {
+          const int v = v0 + d;
+          if (v < KT) {
+            const unsigned char *arow = lds + g * UNIT_PLANE + (wave * 16 + n + v) * 16;
+            Frag8<T> a, b;
+            if constexpr (sizeof(T) == 2) {
+              a.v = *reinterpret_cast<const bf16x8 *>(arow + r * 4 * UNIT_PLANE);
+            } else {
+              a.lo = *reinterpret_cast<const f32x4 *>(arow + r * 4 * UNIT_PLANE);
+            }
+#pragma unroll
+            for (int q = 0; q < 4; ++q) band[d][q] = __builtin_amdgcn_update_dpp(0, band[d][q], 0x111, 0xf, 0xf, true);
+            if (r < KT) {
+              const i32x4 head = *reinterpret_cast<const i32x4 *>(wl + (v * KT + r) * CIN + pass * CHL + g * EPU);
+              if (n == 0) band[d] = head;
+            }
+            __builtin_memcpy(&b, &band[d], 16);
+            if constexpr (sizeof(T) == 4) b.hi = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+            mma16<T>(a, b, acc[d]);
+          }
         }
-        const int u = r - n;  // filter row that links input row r to output row n
-        const bool band = u >= 0 && u < KT;
-        const T *wp = wv + (band ? u : 0) * CIN;
-        if constexpr (sizeof(T) == 2) {
-          b.v = *reinterpret_cast<const bf16x8 *>(wp);
-          if (!band) b = frag_zero<T>();
-        } else {
-          b.lo = *reinterpret_cast<const f32x4 *>(wp);
-          if (!band) b.lo = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-        }
-        mma16<T>(a, b, acc);
       }
     }
   }
+  f32x4 accs = acc[0] + acc[1] + acc[2] + acc[3];
   // lane holds output row n, columns 4g .. 4g+3 of the wave's 16
   const int gi = bi0 + n;
   if (gi >= H) return;
@@ -359,7 +394,7 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   for (int e = 0; e < 4; ++e) {
     const int gj = gj0 + e;
     if (gj >= W) break;
-    float v = acc[e];
+    float v = accs[e];
     if (bias) v += bias_pp ? bias[(long)gi * W + gj] : bias[0];
     out[((long)img * H + gi) * W + gj] = relu ? fmaxf(v, 0.0f) : v;
   }

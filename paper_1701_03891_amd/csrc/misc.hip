@@ -219,6 +219,60 @@ hipError_t pack_fc_fp8(const float *w, u8 *out, int N, int M, int Mpad, float in
   return hipGetLastError();
 }
 
+// ------------------------------------------------ learnable FC layer gradient
+// dW_fc[p][m] = sum_b g[b][p] y[b][m]  (g = dL/dx~ [B][N], y [B][ldy]); fixed order over b.
+template <typename TG, typename Acc>
+__global__ void fc_wgrad_kernel(const TG *__restrict__ g, const float *__restrict__ y, long ldy, int B, int N, int M,
+                                float *__restrict__ dw) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)N * M) return;
+  const int p = (int)(idx / M), m = (int)(idx % M);
+  Acc s = 0;
+  for (int b = 0; b < B; ++b) s += (Acc)g[(long)b * N + p] * (Acc)y[(long)b * ldy + m];
+  dw[idx] = (float)s;
+}
+hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s) {
+  const long n = (long)N * M;
+  if (n > 0) fc_wgrad_kernel<float, float><<<GRID1(n), 0, s>>>(g, y, ldy, B, N, M, dw);
+  return hipGetLastError();
+}
+hipError_t fc_wgrad_f64(const double *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s) {
+  const long n = (long)N * M;
+  if (n > 0) fc_wgrad_kernel<double, double><<<GRID1(n), 0, s>>>(g, y, ldy, B, N, M, dw);
+  return hipGetLastError();
+}
+
+// ------------------------------------------------------ noisy measurements
+// y_b += s_b e_b with ||y_b||^2 / ||s_b e_b||^2 = 10^(snr_db/10); one block per
+// measurement vector, FP64 norms in a fixed order.
+__global__ __launch_bounds__(256) void add_noise_kernel(float *__restrict__ y, const float *__restrict__ e, int M,
+                                                        double snr_db) {
+  __shared__ double ry[256], re[256];
+  const int b = blockIdx.x, tid = threadIdx.x;
+  double sy = 0.0, se = 0.0;
+  for (int m = tid; m < M; m += 256) {
+    const double a = y[(long)b * M + m], c = e[(long)b * M + m];
+    sy += a * a;
+    se += c * c;
+  }
+  ry[tid] = sy;
+  re[tid] = se;
+  __syncthreads();
+  for (int h = 128; h > 0; h >>= 1) {
+    if (tid < h) {
+      ry[tid] += ry[tid + h];
+      re[tid] += re[tid + h];
+    }
+    __syncthreads();
+  }
+  const double s = re[0] > 0.0 ? sqrt(ry[0] / re[0]) * pow(10.0, -snr_db / 20.0) : 0.0;
+  for (int m = tid; m < M; m += 256) y[(long)b * M + m] = (float)((double)y[(long)b * M + m] + s * e[(long)b * M + m]);
+}
+hipError_t add_noise(float *y, const float *e, int B, int M, double snr_db, hipStream_t s) {
+  if (B > 0) add_noise_kernel<<<B, 256, 0, s>>>(y, e, M, snr_db);
+  return hipGetLastError();
+}
+
 // ------------------------------------------------------ loss and metrics
 // One block per image, FP64 reductions in a fixed order.
 // stats[b][4] = { ||xh-x||^2, PSNR (peak = max x), ||xh-x||/||x||, success (ratio <= 0.1) }

@@ -182,3 +182,20 @@ def test_error_paths(dsi):
     # B = 0 is a no-op
     assert _lib.lib().dsi_recover(ctx.h, net.h, None, None, 0, None) == _lib.DSI_OK
     net.free()
+
+
+def test_measure_noisy_parity(dsi):
+    """Noisy measurements at 20 dB (Sec. 5, Table 3) against the oracle's noise model."""
+    import torch
+
+    import oracle
+    import synth
+    P, ctx = dsi
+    M, n, B = 410, 64, 6
+    phi = synth.make_phi(M, n * n, cfg_id=51)
+    x = synth.piecewise_smooth_images(B, n, cfg_id=51).reshape(B, -1)
+    e = synth.normal_values((B, M), 1.0, 51, 7)
+    ref = oracle.add_noise(oracle.measure(phi, x), e, 20.0)
+    t = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")  # noqa: E731
+    got = ctx.measure_noisy(t(phi), t(x), t(e), 20.0).cpu().numpy().astype(np.float64)
+    assert relerr_per_image(got, ref).max() <= 1e-5

@@ -32,6 +32,8 @@ MUTANTS = {
     "dgrad_index": ("int t1 = i + (k - 1) - u, t2 = j + (k - 1) - v;", "int t1 = i + u, t2 = j + (k - 1) - v;"),
     "adam_no_bias_correction": ("double mh = m[q] / c1, vh = v[q] / c2;", "double mh = m[q], vh = v[q] / c2;"),
     "psnr_peak": ("if (x[p] > peak) peak = x[p];", ""),
+    "noise_scale": ("const double s = ne > 0.0 ? sqrt(ny / ne) * pow(10.0, -snr_db / 20.0) : 0.0;",
+                    "const double s = ne > 0.0 ? sqrt(ny / ne) * pow(10.0, -snr_db / 10.0) : 0.0;"),
     "dct_sign": ("C[(long)k * n + i] = a * cos(pi * (2 * i + 1) * k / (2.0 * n));",
                  "C[(long)k * n + i] = a * cos(pi * (2 * i - 1) * k / (2.0 * n));"),
 }

@@ -319,3 +319,18 @@ def test_p17_ista_recovers_sparse_exactly_32(orc):
     y = orc.measure(phi, x.reshape(1, -1))[0]
     xr, s, ns = orc.ista_dct(phi, y, n, n, stages=12, iters=300)
     assert np.linalg.norm(xr - x.reshape(-1)) / np.linalg.norm(x) < 1e-9
+
+
+def test_noise_reaches_the_requested_snr(orc):
+    """Sec. 5 / Table 3 noise model: the added noise has exactly the requested SNR and direction."""
+    y = synth.normal_values((3, 40), 1.0, 117, 1)
+    e = synth.normal_values((3, 40), 1.0, 117, 2)
+    yn = orc.add_noise(y, e, 20.0)
+    d = yn - y
+    snr = 10 * np.log10((y ** 2).sum(axis=1) / (d ** 2).sum(axis=1))
+    np.testing.assert_allclose(snr, 20.0, atol=1e-12)
+    for b in range(3):   # d is a positive multiple of e
+        c = np.dot(d[b], e[b]) / np.dot(e[b], e[b])
+        assert c > 0
+        np.testing.assert_allclose(d[b], c * e[b], atol=1e-14)
+    assert np.array_equal(orc.add_noise(y, np.zeros_like(e), 20.0), y)
