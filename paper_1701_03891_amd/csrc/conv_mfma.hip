@@ -78,6 +78,37 @@ template <> DSI_INLINE void load4f<bf16>(const bf16 *src, float *o) {
   o[0] = (float)v[0]; o[1] = (float)v[1]; o[2] = (float)v[2]; o[3] = (float)v[3];
 }
 
+// ------------------------------------------------------------------ LDS staging
+// Copies NU 16-byte units into LDS.  unit(idx, loff) returns the global address
+// of unit idx (nullptr: outside the image, zero-filled) and sets its LDS byte
+// offset.  A thread issues the loads of a whole batch of its units before it
+// stores any of them, so their HBM/L2 latencies overlap instead of adding up.
+// MAXB bounds the batch (registers held by the loads in flight).
+template <int NU, int NT, int MAXB = 16, typename F>
+DSI_INLINE void stage_units(unsigned char *lds, int tid, F unit) {
+  constexpr int NIT = (NU + NT - 1) / NT;
+  constexpr int NB = (NIT + MAXB - 1) / MAXB;        // batches
+  constexpr int BATCH = (NIT + NB - 1) / NB;         // balanced batch size <= MAXB
+#pragma unroll
+  for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+    i32x4 v[BATCH];
+    int lo[BATCH];
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j) {
+      const int idx = tid + (b0 + j) * NT;
+      v[j] = i32x4{0, 0, 0, 0};
+      lo[j] = -1;
+      if (b0 + j < NIT && idx < NU) {
+        const void *g = unit(idx, lo[j]);
+        if (g) v[j] = *reinterpret_cast<const i32x4 *>(g);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j)
+      if (lo[j] >= 0) *reinterpret_cast<i32x4 *>(lds + lo[j]) = v[j];
+  }
+}
+
 // ===================================================================== conv_mid
 // in   [B][CIN/SC][H][W][SC]  (T; SC = 16 channels per slice, 64 for FP8)
 // wp   [CIN/SC][11 v][11 u][COUT/32][64 lanes][FE]  (T; FE = 8, 32 for FP8): lane l holds
@@ -117,15 +148,16 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   for (int cs = 0; cs < NCS; ++cs) {
     __syncthreads();  // previous slice fully consumed
     const T *src = in + (long)(img * NCS + cs) * H * W * SC;
-    for (int idx = tid; idx < LH * LW * CH16; idx += NT) {
-      const int chunk = idx / (LH * LW), pix = idx - chunk * (LH * LW);
+    // consecutive threads take consecutive 16-byte chunks of a pixel row (coalesced)
+    // (wider types keep fewer loads in flight: their weight fragments need the registers)
+    stage_units<LH * LW * CH16, NT, sizeof(T) == 2 ? 16 : 2>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int chunk = idx % CH16, pix = idx / CH16;
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-      i32x4 val = {0, 0, 0, 0};
-      if (gi >= 0 && gi < H && gj >= 0 && gj < W)
-        val = *reinterpret_cast<const i32x4 *>(src + ((long)gi * W + gj) * SC + chunk * (16 / (int)sizeof(T)));
-      *reinterpret_cast<i32x4 *>(lds + (row * CH16 + chunk) * PLANE + col * 16) = val;
-    }
+      loff = (row * CH16 + chunk) * PLANE + col * 16;
+      if (gi < 0 || gi >= H || gj < 0 || gj >= W) return nullptr;
+      return src + ((long)gi * W + gj) * SC + chunk * (16 / (int)sizeof(T));
+    });
     __syncthreads();
     const T *wcs = wp + (long)cs * KT * KT * NCT * 64 * FE + lane * FE;
     Frag8<T> wf[KT][NCT], wn[KT][NCT];
@@ -204,69 +236,121 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
 // staged), wp [11 u][COUT/32][64][8] (T): lane l holds
 //     W[co = ct*32 + l%32][0][u][v = 8*(l/32) + e] (0 for v >= 11)
 // out [B][COUT/16][H][W][16] (TO).
+// A block owns a 4-row x 32-column tile of up to FIRST_IMGS images (one output
+// row per wave) and stages all of their input halos in LDS at once.  Each wave
+// keeps its bias values (and, for 2-byte types, all 11 x COUT/32 weight
+// fragments) in registers across the images, so per image it only reads 11 LDS
+// fragments, issues 11 x COUT/32 MFMAs and stores its row.
 // The B operand of the k-step for filter row u is 8 consecutive pixels of one
 // LDS row, read with one unaligned 16-byte LDS load.
 // EPI_BIAS: out = ReLU?(acc + bias);  EPI_MASK: out = acc * (mask > 0).
 // An FP8 output (TO = u8) is quantised as code = e4m3(oscale * value) into 64-channel slices.
+constexpr int FIRST_IMGS = 16;
+
 template <typename T, int COUT, int EPI, typename TI, typename TO>
 __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ in, const T *__restrict__ wp,
                                                          const float *__restrict__ bias, int bias_pp, int relu,
-                                                         const T *__restrict__ mask, TO *__restrict__ out,
-                                                         int H, int W, int tiles_w, int tiles_per_img, float oscale) {
+                                                         const T *__restrict__ mask, TO *__restrict__ out, int B,
+                                                         int H, int W, int tiles_w, int tiles_per_img, int ipb,
+                                                         float oscale) {
   constexpr int OSC = slice_ch<TO>();
-  constexpr int ROWS = 4, TH = 4 * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
+  constexpr int TH = 4, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
   constexpr int LWA = LW + 8;  // zero columns so the 8-wide reads of the last lanes stay in the tile
   constexpr int NCT = COUT / 32;
-  __shared__ __attribute__((aligned(16))) T tile[LH * LWA];
+  constexpr bool WREG = sizeof(T) == 2;  // weights resident in registers
+  __shared__ __attribute__((aligned(16))) T tile[FIRST_IMGS * LH * LWA];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
-  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  const int grp = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  const int img0 = grp * ipb, nimg = min(ipb, B - img0);
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  const TI *src = in + (long)img * H * W;
-  for (int idx = tid; idx < LH * LWA; idx += 256) {
-    const int row = idx / LWA, col = idx - row * LWA;
-    const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-    const bool inside = col < LW && gi >= 0 && gi < H && gj >= 0 && gj < W;
-    tile[idx] = from_f32<T>(inside ? to_f32(src[(long)gi * W + gj]) : 0.0f);
-  }
-  __syncthreads();
-
-  // all ROWS x NCT accumulators live; filter rows u outermost, so each k-step issues
-  // ROWS * NCT independent MFMAs and the next row's weight fragments load meanwhile
-  f32x16 acc[ROWS][NCT];
+  {
+    // element loads: a batch of 16 per thread in flight before their LDS stores
+    constexpr int NE = FIRST_IMGS * LH * LWA, NIT = (NE + 255) / 256, BATCH = 16;
+    const int ne = nimg * LH * LWA;
 #pragma unroll
-  for (int ri = 0; ri < ROWS; ++ri)
+    for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+      float v[BATCH];
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) {
+        const int idx = tid + (b0 + j) * 256;
+        v[j] = 0.0f;
+        if (b0 + j < NIT && idx < ne) {
+          const int im = idx / (LH * LWA), rem = idx - im * (LH * LWA);
+          const int row = rem / LWA, col = rem - row * LWA;
+          const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+          if (col < LW && gi >= 0 && gi < H && gj >= 0 && gj < W) v[j] = to_f32(in[((long)(img0 + im) * H + gi) * W + gj]);
+        }
+      }
+#pragma unroll
+      for (int j = 0; j < BATCH; ++j) {
+        const int idx = tid + (b0 + j) * 256;
+        if (b0 + j < NIT && idx < ne) tile[idx] = from_f32<T>(v[j]);
+      }
+    }
+  }
+
+  const int gi = bi0 + wave, gj = bj0 + px;
+  const bool live = gi < H && gj < W;
+  float bv[NCT][4][4];
+  if constexpr (EPI == EPI_BIAS) {
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[ri][c][r] = 0.0f;
-  Frag8<T> wf[NCT], wn[NCT];
+      for (int q = 0; q < 4; ++q) {
+        const int co0 = c * 32 + 8 * q + 4 * h;
+        if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
 #pragma unroll
-  for (int c = 0; c < NCT; ++c) wf[c] = frag_load<T>(wp + (c * 64 + lane) * 8);
+          for (int e = 0; e < 4; ++e) bv[c][q][e] = live ? bias[((long)(co0 + e) * H + gi) * W + gj] : 0.0f;
+        } else {
+          load4f<float>(bias + co0, bv[c][q]);
+        }
+      }
+  }
+  Frag8<T> wr[WREG ? KT : 1][NCT];
+  if constexpr (WREG) {
 #pragma unroll
-  for (int u = 0; u < KT; ++u) {
-    if (u + 1 < KT) {
+    for (int u = 0; u < KT; ++u)
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) wn[c] = frag_load<T>(wp + (((u + 1) * NCT + c) * 64 + lane) * 8);
+      for (int c = 0; c < NCT; ++c) wr[u][c] = frag_load<T>(wp + ((u * NCT + c) * 64 + lane) * 8);
+  }
+  __syncthreads();
+
+  for (int im = 0; im < nimg; ++im) {
+    const int img = img0 + im;
+    float mv[NCT][4][4];
+    if constexpr (EPI == EPI_MASK) {  // issued before the MFMAs so their latency overlaps
+#pragma unroll
+      for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const int co0 = c * 32 + 8 * q + 4 * h;
+          const long o = ((((long)img * (COUT / OSC) + co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC;
+          if (live) load4f<T>(mask + o, mv[c][q]);
+        }
     }
+    f32x16 acc[NCT];
 #pragma unroll
-    for (int ri = 0; ri < ROWS; ++ri) {
+    for (int c = 0; c < NCT; ++c)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
+    const T *trow = tile + (im * LH + wave) * LWA + px + 8 * h;
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
       // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e (unaligned)
       Frag8<T> xf;
-      __builtin_memcpy(&xf, tile + (wave * ROWS + ri + u) * LWA + px + 8 * h, sizeof(xf));
+      __builtin_memcpy(&xf, trow + u * LWA, sizeof(xf));
       if (h) xf = frag_keep_first<T, 3>(xf);  // taps v >= 11 are padding: keep them finite-free
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) wf[c].mma(xf, acc[ri][c]);
+      for (int c = 0; c < NCT; ++c) {
+        if constexpr (WREG) {
+          wr[u][c].mma(xf, acc[c]);
+        } else {
+          const Frag8<T> wf = frag_load<T>(wp + ((u * NCT + c) * 64 + lane) * 8);
+          wf.mma(xf, acc[c]);
+        }
+      }
     }
-#pragma unroll
-    for (int c = 0; c < NCT; ++c) wf[c] = wn[c];
-  }
-
-  const int gj = bj0 + px;
-#pragma unroll
-  for (int ri = 0; ri < ROWS; ++ri) {
-    const int lr = wave * ROWS + ri;
-    const int gi = bi0 + lr;
-    if (gi >= H || gj >= W) continue;
+    if (!live) continue;
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
@@ -275,25 +359,16 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         const long o = ((((long)img * (COUT / OSC) + co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC;
         float vals[4];
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vals[e] = acc[ri][c][4 * q + e];
+        for (int e = 0; e < 4; ++e) vals[e] = acc[c][4 * q + e];
         if constexpr (EPI == EPI_BIAS) {
-          float bv[4];
-          if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bv[e] = bias[((long)(co0 + e) * H + gi) * W + gj];
-          } else {
-            load4f<float>(bias + co0, bv);
-          }
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            vals[e] += bv[e];
+            vals[e] += bv[c][q][e];
             if (relu) vals[e] = fmaxf(vals[e], 0.0f);
           }
         } else {
-          float mv[4];
-          load4f<T>(mask + o, mv);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) vals[e] = mv[e] > 0.0f ? vals[e] : 0.0f;
+          for (int e = 0; e < 4; ++e) vals[e] = mv[c][q][e] > 0.0f ? vals[e] : 0.0f;
         }
         if constexpr (sizeof(TO) == 1) {
 #pragma unroll
@@ -339,16 +414,15 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   for (int pass = 0; pass < NPASS; ++pass) {
     __syncthreads();
     // stage 16-byte units: unit q of pixel covers channels pass*CHL + q*EPU .. +EPU
-    for (int idx = tid; idx < LH * LW * 4; idx += 256) {
-      const int q = idx / (LH * LW), pix = idx - q * (LH * LW);
+    stage_units<LH * LW * 4, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int q = idx % 4, pix = idx / 4;
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
       const int c0 = pass * CHL + q * EPU;
-      i32x4 val = {0, 0, 0, 0};
-      if (gi >= 0 && gi < H && gj >= 0 && gj < W)
-        val = *reinterpret_cast<const i32x4 *>(in + ((((long)img * (CIN / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
-      *reinterpret_cast<i32x4 *>(lds + (row * 4 + q) * UNIT_PLANE + col * 16) = val;
-    }
+      loff = (row * 4 + q) * UNIT_PLANE + col * 16;
+      if (gi < 0 || gi >= H || gj < 0 || gj >= W) return nullptr;
+      return in + ((((long)img * (CIN / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15);
+    });
     __syncthreads();
     // four tap columns at a time: four independent accumulator chains per row step
     for (int v0 = 0; v0 < KT; v0 += 4) {
@@ -400,6 +474,86 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   }
 }
 
+// BF16 variant: one 16-channel slice per pass and K = 32 packing two horizontal
+// taps (v = 2p, 2p + 1) x 16 channels, so a pass holds only 32 bytes per pixel
+// in LDS (62 KiB per block, two blocks per CU) and a tap pair costs one MFMA.
+// Lane group g = l/16 holds K slots 8g .. 8g+7: channels 8(g&1) .. +7 of tap
+// v = 2p + (g>>1).  The sixth pair's second tap (v = 11) has a zero weight band;
+// its activations come from one extra LDS column that is zero-filled.
+// wt [11 v][11 u][CIN] (bf16), staged in LDS with a zero v = 11 plane.
+template <int CIN>
+__global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wt,
+                                                             const float *__restrict__ bias, int bias_pp, int relu,
+                                                             float *__restrict__ out, int H, int W, int tiles_w,
+                                                             int tiles_per_img) {
+  constexpr int TH = 16, TW = 64, LH = TH + 2 * RAD, LW = TW + 2 * RAD + 1;
+  constexpr int NP = (KT + 1) / 2;          // tap pairs
+  constexpr int UNIT_PLANE = LW * 16;       // bytes between the two 8-channel planes of an LDS row
+  constexpr int NS = CIN / 16;              // 16-channel slices = passes
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * 2 * UNIT_PLANE];
+  __shared__ __attribute__((aligned(16))) bf16 wl[(KT + 1) * KT * CIN];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
+  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
+  for (int idx = tid; idx < (KT + 1) * KT * CIN; idx += 256) wl[idx] = idx < KT * KT * CIN ? wt[idx] : (bf16)0.0f;
+  f32x4 acc[NP];
+#pragma unroll
+  for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+  // this lane's LDS column for tap pair 0 and its 8-channel plane
+  const unsigned char *abase = lds + (g & 1) * UNIT_PLANE + (wave * 16 + n + (g >> 1)) * 16;
+  for (int sl = 0; sl < NS; ++sl) {
+    __syncthreads();
+    const bf16 *src = in + (long)(img * NS + sl) * H * W * 16;
+    stage_units<LH * LW * 2, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int q = idx & 1, pix = idx >> 1;
+      const int row = pix / LW, col = pix - row * LW;
+      const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+      loff = (row * 2 + q) * UNIT_PLANE + col * 16;
+      if (col >= LW - 1 || gi < 0 || gi >= H || gj < 0 || gj >= W) return nullptr;
+      return src + ((long)gi * W + gj) * 16 + q * 8;
+    });
+    __syncthreads();
+    // Band operand of pair p at input row r: B[k][i] = W[c][u = r - i][v], zero outside
+    // 0 <= u <= 10; row r's band is row r-1's shifted by one lane within each 16-lane
+    // group (DPP row_shr:1, zero into lane 0), lane 0 taking W[u = r] while r <= 10.
+    i32x4 band[NP];
+#pragma unroll
+    for (int p = 0; p < NP; ++p) band[p] = i32x4{0, 0, 0, 0};
+    const bf16 *whead = wl + (g >> 1) * KT * CIN + sl * 16 + 8 * (g & 1);
+#pragma unroll
+    for (int r = 0; r < LH; ++r) {
+#pragma unroll
+      for (int p = 0; p < NP; ++p) {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) band[p][q] = __builtin_amdgcn_update_dpp(0, band[p][q], 0x111, 0xf, 0xf, true);
+        if (r < KT) {
+          const i32x4 head = *reinterpret_cast<const i32x4 *>(whead + (2 * p * KT + r) * CIN);
+          if (n == 0) band[p] = head;
+        }
+        Frag8<bf16> a, b;
+        a.v = *reinterpret_cast<const bf16x8 *>(abase + r * 2 * UNIT_PLANE + 2 * p * 16);
+        __builtin_memcpy(&b, &band[p], 16);
+        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[p], 0, 0, 0);
+      }
+    }
+  }
+  f32x4 accs = acc[0];
+#pragma unroll
+  for (int p = 1; p < NP; ++p) accs += acc[p];
+  // lane holds output row n, columns 4g .. 4g+3 of the wave's 16
+  const int gi = bi0 + n;
+  if (gi >= H) return;
+  const int gj0 = bj0 + wave * 16 + 4 * g;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) {
+    const int gj = gj0 + e;
+    if (gj >= W) break;
+    float v = accs[e];
+    if (bias) v += bias_pp ? bias[(long)gi * W + gj] : bias[0];
+    out[((long)img * H + gi) * W + gj] = relu ? fmaxf(v, 0.0f) : v;
+  }
+}
+
 template <> DSI_INLINE void mma16<bf16>(const Frag8<bf16> &a, const Frag8<bf16> &b, f32x4 &acc) {
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
 }
@@ -419,9 +573,13 @@ hipError_t conv_first(const TI *in, const T *wp, const float *bias, int bias_pp,
                       TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
   int tw, tpi;
-  tiles(H, W, 16, 32, tw, tpi);
+  tiles(H, W, 4, 32, tw, tpi);
+  // images per block: enough blocks for two per CU, at most FIRST_IMGS
+  const long want = ((long)B * tpi + 511) / 512;
+  const int ipb = (int)std::max(1L, std::min((long)FIRST_IMGS, want));
+  const int groups = (B + ipb - 1) / ipb;
   conv_first_kernel<T, COUT, EPI, TI, TO>
-      <<<B * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
+      <<<groups * tpi, 256, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, B, H, W, tw, tpi, ipb, oscale);
   return hipGetLastError();
 }
 
@@ -429,9 +587,9 @@ template <typename T, int CIN, int COUT, int EPI, typename TO>
 hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
                     TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
-  constexpr int ROWS = COUT == 32 ? 8 : 4;
   // BF16 with 32 outputs: 8 waves (two per SIMD) on a 64 x 32 tile; its 74-row halo
-  // slice (99 KiB of LDS) fits one block per CU.  Wider types keep 4 waves.
+  // slice (99 KiB of LDS) fits one block per CU.  Other types keep 4 waves.
+  constexpr int ROWS = COUT == 32 ? 8 : 4;
   constexpr int WAVES = (sizeof(T) == 2 && COUT == 32) ? 8 : 4;
   int tw, tpi;
   tiles(H, W, WAVES * ROWS, 32, tw, tpi);
@@ -446,7 +604,10 @@ hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, in
   if (B <= 0) return hipSuccess;
   int tw, tpi;
   tiles(H, W, 16, 64, tw, tpi);
-  conv_last_kernel<T, CIN><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
+  if constexpr (sizeof(T) == 2)
+    conv_last_bf16_kernel<CIN><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
+  else
+    conv_last_kernel<T, CIN><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
   return hipGetLastError();
 }
 

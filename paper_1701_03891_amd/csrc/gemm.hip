@@ -23,30 +23,42 @@ DSI_INLINE void load8_checked(const TS *base, long ld, int row, int k, int K, fl
   for (int e = 0; e < 8; ++e) out[e] = (k + e < K) ? to_f32(p[e]) : 0.0f;
 }
 
-template <typename TS, typename TM> struct Loader;
-// fast path: rows padded to a multiple of 16 elements, 16-byte aligned
-template <> struct Loader<bf16, bf16> {
-  static DSI_INLINE Frag8<bf16> ld(const bf16 *p) { return frag_load<bf16>(p); }
+// Raw 8-element operand as loaded (no conversion yet, so a prefetched load is
+// not waited for until its k-step), then converted to the MFMA input type.
+template <typename TS> struct Raw8;
+template <> struct Raw8<bf16> {
+  bf16x8 v;
+  DSI_INLINE void ld(const bf16 *p) { v = *reinterpret_cast<const bf16x8 *>(p); }
 };
-template <> struct Loader<float, float> {
-  static DSI_INLINE Frag8<float> ld(const float *p) { return frag_load<float>(p); }
-};
-template <> struct Loader<float, bf16> {
-  static DSI_INLINE Frag8<bf16> ld(const float *p) {
-    f32x4 a = *reinterpret_cast<const f32x4 *>(p), b = *reinterpret_cast<const f32x4 *>(p + 4);
-    float x[8] = {a[0], a[1], a[2], a[3], b[0], b[1], b[2], b[3]};
-    return frag_from<bf16>(x);
+template <> struct Raw8<float> {
+  f32x4 a, b;
+  DSI_INLINE void ld(const float *p) {
+    a = *reinterpret_cast<const f32x4 *>(p);
+    b = *reinterpret_cast<const f32x4 *>(p + 4);
   }
 };
-template <> struct Loader<bf16, float> {
-  static DSI_INLINE Frag8<float> ld(const bf16 *p) {
-    bf16x8 v = *reinterpret_cast<const bf16x8 *>(p);
-    float x[8];
+template <typename TM, typename TS> DSI_INLINE Frag8<TM> to_frag(const Raw8<TS> &r);
+template <> DSI_INLINE Frag8<bf16> to_frag<bf16, bf16>(const Raw8<bf16> &r) {
+  Frag8<bf16> f;
+  f.v = r.v;
+  return f;
+}
+template <> DSI_INLINE Frag8<float> to_frag<float, float>(const Raw8<float> &r) {
+  Frag8<float> f;
+  f.lo = r.a;
+  f.hi = r.b;
+  return f;
+}
+template <> DSI_INLINE Frag8<bf16> to_frag<bf16, float>(const Raw8<float> &r) {
+  float x[8] = {r.a[0], r.a[1], r.a[2], r.a[3], r.b[0], r.b[1], r.b[2], r.b[3]};
+  return frag_from<bf16>(x);
+}
+template <> DSI_INLINE Frag8<float> to_frag<float, bf16>(const Raw8<bf16> &r) {
+  float x[8];
 #pragma unroll
-    for (int e = 0; e < 8; ++e) x[e] = (float)v[e];
-    return frag_from<float>(x);
-  }
-};
+  for (int e = 0; e < 8; ++e) x[e] = (float)r.v[e];
+  return frag_from<float>(x);
+}
 
 // C[b][o] = scale * sum_k X[b][k] W[o][k];  X [Bn][ldx] (TX), W [O][ldw] (TW), C [Bn][ldc] (TC).
 // VEC: K % 16 == 0, ldx/ldw multiples of 8, pointers 16-byte aligned.
@@ -66,12 +78,33 @@ __global__ __launch_bounds__(256) void gemm_nt_kernel(const TX *__restrict__ X, 
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   if constexpr (VEC) {
+    // software pipeline: the operands of the next PF k-steps are in flight while
+    // the current one multiplies (the loop is otherwise bound by L2 latency)
+    constexpr int PF = 8;
     const TX *px = X + (long)rb * ldx + kh;
     const TW *pw = W + (long)ro * ldw + kh;
-    for (int k0 = 0; k0 < K; k0 += 16) {
-      Frag8<TM> fx = Loader<TX, TM>::ld(px + k0);
-      Frag8<TM> fw = Loader<TW, TM>::ld(pw + k0);
-      fx.mma(fw, acc);
+    const int nk = K / 16;
+    Raw8<TX> rx[PF];
+    Raw8<TW> rw[PF];
+#pragma unroll
+    for (int p = 0; p < PF; ++p)
+      if (p < nk) {
+        rx[p].ld(px + p * 16);
+        rw[p].ld(pw + p * 16);
+      }
+    for (int k = 0; k < nk; k += PF) {
+#pragma unroll
+      for (int p = 0; p < PF; ++p) {
+        if (k + p < nk) {
+          const Frag8<TM> fx = to_frag<TM>(rx[p]), fw = to_frag<TM>(rw[p]);
+          fx.mma(fw, acc);
+          const int kn = k + p + PF;
+          if (kn < nk) {
+            rx[p].ld(px + kn * 16);
+            rw[p].ld(pw + kn * 16);
+          }
+        }
+      }
     }
   } else {
     for (int k0 = 0; k0 < K; k0 += 16) {
@@ -107,9 +140,27 @@ __global__ __launch_bounds__(256) void gemm_nt_fp8_kernel(const u8 *__restrict__
 #pragma unroll
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   const u8 *px = X + (long)rb * ldx + kh, *pw = W + (long)ro * ldw + kh;
-  for (int k0 = 0; k0 < K; k0 += 64) {
-    Frag8<u8> fx = frag_load<u8>(px + k0), fw = frag_load<u8>(pw + k0);
-    fx.mma(fw, acc);
+  constexpr int PF = 4;  // k-steps in flight
+  const int nk = K / 64;
+  Frag8<u8> fx[PF], fw[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p)
+    if (p < nk) {
+      fx[p] = frag_load<u8>(px + p * 64);
+      fw[p] = frag_load<u8>(pw + p * 64);
+    }
+  for (int k = 0; k < nk; k += PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      if (k + p < nk) {
+        fx[p].mma(fw[p], acc);
+        const int kn = k + p + PF;
+        if (kn < nk) {
+          fx[p] = frag_load<u8>(px + kn * 64);
+          fw[p] = frag_load<u8>(pw + kn * 64);
+        }
+      }
+    }
   }
   const int o = o0 + (lane & 31);
   if (o >= O) return;
