@@ -107,6 +107,74 @@ def time_path(ctx, net, y, steps, warmup, torch, stage_timing):
     return dict(total_ms=total_ms, wall_s=wall, per_step_ms=per, stages=stages, xhat=xh)
 
 
+def time_recover(net, y, n1, n2, steps, warmup, torch):
+    """Average ms per dsi_recover of the batch y (events on the current stream)."""
+    B = y.shape[0]
+    xh = torch.empty((B, n1, n2), dtype=torch.float32, device=y.device)
+    for _ in range(warmup):
+        net.recover(y, xh)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    e0.record()
+    for _ in range(steps):
+        net.recover(y, xh)
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / steps, xh
+
+
+def c4_leg(ctx, P, torch, steps, warmup):
+    """128 x 128 images, M = 4096 (a 16384 x 4096 FC layer), batch 64, He-initialised:
+    FP8 (static power-of-two scales) and BF16 recovery rates."""
+    import synth
+    n, Mc, B = 128, 4096, 64
+    dev = "cuda:0"
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    phi = synth.make_phi(Mc, n * n, cfg_id=4)
+    x = synth.piecewise_smooth_images(B, n, n, cfg_id=4).reshape(B, -1)
+    prm = synth.he_init(synth.PAPER_ARCH, n, n, bias_per_pixel=True, cfg_id=4)
+    params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+    phi_d = t(phi)
+    y = ctx.measure(phi_d, t(x))
+    xc = synth.piecewise_smooth_images(32, n, n, cfg_id=901, stream=synth.STREAM_CALIB).reshape(32, -1)
+    yc = ctx.measure(phi_d, t(xc))
+    out = {"workload": "128x128 images, M=4096 (FC 16384x4096), batch 64, He-init, piecewise-smooth"}
+    xh = {}
+    for prec in ("fp8", "bf16"):
+        net = ctx.prepare(n, n, Mc, params, prec=prec)
+        if prec == "fp8":
+            net.calibrate(yc)
+        net.reserve(B)
+        ms, xr = time_recover(net, y, n, n, steps, warmup, torch)
+        out[prec] = {"images_per_s": B / (ms / 1e3), "ms_per_batch": ms}
+        xh[prec] = xr.cpu().numpy().reshape(B, -1)
+        net.free()
+    del params, phi_d
+    return out, {"phi": phi, "x": x, "prm": prm, "y": y.cpu().numpy().astype(np.float64), "xhat": xh}
+
+
+def c1_leg(ctx, P, torch, steps, warmup):
+    """32 x 32 DCT-sparse signals (K = 40), M = 256: recovery time per image of the network
+    (He-init; its run time does not depend on the weights) at batch 8 and batch 256."""
+    import synth
+    n, Mc = 32, 256
+    dev = "cuda:0"
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    phi = synth.make_phi(Mc, n * n, cfg_id=1)
+    x = synth.dct_sparse_images(256, n, 40, cfg_id=1).reshape(256, -1)
+    prm = synth.he_init(synth.PAPER_ARCH, n, n, bias_per_pixel=True, cfg_id=1)
+    params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+    y = ctx.measure(t(phi), t(x))
+    net = ctx.prepare(n, n, Mc, params, prec="bf16")
+    net.reserve(256)
+    out = {"workload": "32x32 DCT-sparse (K=40), M=256, BF16"}
+    for B in (8, 256):
+        ms, _ = time_recover(net, y[:B].contiguous(), n, n, steps, warmup, torch)
+        out[f"batch{B}"] = {"ms_per_batch": ms, "us_per_image": ms * 1e3 / B}
+    net.free()
+    return out, {"phi": phi, "x": x, "y": y.cpu().numpy().astype(np.float64)}
+
+
 def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=1e-3, pool=1024):
     """Adam training of the network (Sec. 4: MSE loss, backpropagation) on a pool of
     synthetic piecewise-smooth 64x64 images (a different seed from the benchmark
@@ -147,13 +215,19 @@ def calibration_y(ctx, P, torch, phi, B=64):
     return ctx.measure(t(phi), t(xc))
 
 
-def cpu_baseline(phi, x, prm, y_host, xhs, n_img):
-    """The FP64 oracle on the first n_img images of the batch, on this host's cores."""
+def cpu_baseline(phi, x, prm, y_host, xhs, n_img, c4=None, c1=None):
+    """The FP64 oracle on the first n_img images of the batch, on this host's cores
+    (and on one core for a few images); with c4 / c1, the 128 x 128 FP8 accuracy
+    on two sampled images and the classical ISTA-DCT solver's time on one C1 signal."""
     import oracle
     threads = min(16, os.cpu_count() or 1)
-    oracle.set_threads(threads)
     net = oracle.Net(N1, N2, M, bias_full=True)
     bfull = [oracle.full_bias_from_cropped(prm.b[l], 11) for l in range(3)]
+    oracle.set_threads(1)
+    t0 = time.perf_counter()
+    oracle.forward(net, phi.T, prm.w, bfull, y_host[:4])
+    dt1 = time.perf_counter() - t0
+    oracle.set_threads(threads)
     t0 = time.perf_counter()
     ref = oracle.forward(net, phi.T, prm.w, bfull, y_host[:n_img])
     dt = time.perf_counter() - t0
@@ -161,7 +235,8 @@ def cpu_baseline(phi, x, prm, y_host, xhs, n_img):
     ps64 = oracle.psnr(ref, xs)
     out = {"value": n_img / dt, "unit": "images/s", "cores": threads, "kind": "oracle",
            "sample": f"{n_img} of the 256 images of the batch (64x64, M=1024), FP64 C oracle, "
-                     f"{dt:.1f} s on {threads} threads"}
+                     f"{dt:.1f} s on {threads} threads",
+           "single_core": {"value": 4 / dt1, "unit": "images/s", "sample": f"4 images, {dt1:.1f} s on 1 thread"}}
     acc = {}
     for name, xh in xhs.items():
         xh = xh[:n_img].reshape(n_img, -1).astype(np.float64)
@@ -172,6 +247,30 @@ def cpu_baseline(phi, x, prm, y_host, xhs, n_img):
                      "psnr_mean_db": float(oracle.psnr(xh, xs).mean()),
                      "success_rate": float(oracle.success(xh, xs).mean())}
     acc["fp64"] = {"psnr_mean_db": float(ps64.mean()), "success_rate": float(oracle.success(ref, xs).mean())}
+    if c4 is not None:
+        n = 128
+        net4 = oracle.Net(n, n, 4096, bias_full=True)
+        b4 = [oracle.full_bias_from_cropped(c4["prm"].b[l], 11) for l in range(3)]
+        idx = np.array([0, 63])
+        t0 = time.perf_counter()
+        ref4 = oracle.forward(net4, c4["phi"].T, c4["prm"].w, b4, c4["y"][idx])
+        dt4 = time.perf_counter() - t0
+        x4 = c4["x"][idx]
+        a4 = {"sample": f"images 0 and 63 of the 128x128 batch, FP64 oracle {dt4:.1f} s"}
+        for name, xh in c4["xhat"].items():
+            xh = xh[idx].astype(np.float64)
+            a4[name] = {"max_relerr_vs_fp64": float(oracle.relerr(xh, ref4).max()),
+                        "dpsnr_mean_db": float((oracle.psnr(ref4, x4) - oracle.psnr(xh, x4)).mean())}
+        acc["c4_128x128"] = a4
+    if c1 is not None:
+        # the classical sparsity-regularised solver (ISTA in the 2-D DCT basis, 12 x 300
+        # iterations with continuation, then a least-squares debias) on one signal
+        t0 = time.perf_counter()
+        xi, _, _ = oracle.ista_dct(c1["phi"], c1["y"][0], 32, 32)
+        dti = time.perf_counter() - t0
+        out["ista_dct"] = {"seconds_per_image": dti, "threads": 1,
+                           "relerr_vs_truth": float(oracle.relerr(xi[None], c1["x"][:1])[0]),
+                           "sample": "one 32x32 DCT-sparse signal (K=40), M=256"}
     return out, acc
 
 
@@ -185,8 +284,10 @@ def main():
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency under load) leg")
     ap.add_argument("--train-steps", type=int, default=400,
                     help="Adam steps on synthetic images before timing (0: He-init weights)")
-    ap.add_argument("--serve-requests", type=int, default=2000)
-    ap.add_argument("--serve-qps", type=float, default=3000.0)
+    ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests per load point")
+    ap.add_argument("--serve-qps", type=str, default="2000,8000,64000",
+                    help="offered loads (requests/s); the highest should exceed capacity")
+    ap.add_argument("--no-extra", action="store_true", help="skip the 128x128 FP8 and 32x32 legs")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -224,6 +325,11 @@ def main():
         r["xhat_host"] = r["xhat"].cpu().numpy()
         res[prec] = r
         net.free()
+
+    c4 = c4_data = c1 = c1_data = None
+    if not args.no_extra:
+        c4, c4_data = c4_leg(ctx, P, torch, 20, 3)
+        c1, c1_data = c1_leg(ctx, P, torch, 50, 5)
 
     b = res["bf16"]
     ms_step = b["total_ms"] / args.steps
@@ -266,19 +372,28 @@ def main():
                      "traffic_unit": "bytes per launch (rocprofv3 FETCH_SIZE + WRITE_SIZE, calibrated)"},
         "cpu_baseline": None,
         "training": train,
+        "c4_128x128": c4,
+        "c1_32x32": c1,
     }
     if not args.no_cpu:
         y_host = y.cpu().numpy().astype(np.float64)
-        cb, acc = cpu_baseline(phi, x, prm, y_host, {k: res[k]["xhat_host"] for k in res}, args.cpu_images)
+        cb, acc = cpu_baseline(phi, x, prm, y_host, {k: res[k]["xhat_host"] for k in res}, args.cpu_images,
+                               c4=c4_data, c1=c1_data)
         out["cpu_baseline"] = cb
         out["accuracy_vs_fp64_on_sample"] = acc
+        if c1 is not None and "ista_dct" in cb:
+            out["c1_32x32"]["ista_over_network_time_per_image"] = (
+                cb["ista_dct"]["seconds_per_image"] / (c1["batch8"]["us_per_image"] * 1e-6))
     ctx.close()
     if not args.no_serve:
         from paper_1701_03891_amd import serve
-        out["serving"] = serve.run_serving(n_req=args.serve_requests, qps=args.serve_qps, slots=2,
-                                           budget_gib=16.0, warmup=200)
-        out["serving"]["workload"] = ("Poisson arrivals, 1-32 images per request, 9 networks "
-                                      "(32/64/128 px x M/N 0.10/0.25/0.50), BF16, 2 streams, HIP graphs")
+        qps = [float(q) for q in args.serve_qps.split(",") if q]
+        sv = serve.sweep_serving(qps, n_req=args.serve_requests, slots=2, budget_gib=16.0, warmup=1000,
+                                 at_fraction=0.7, log=lambda m: print(m, file=sys.stderr, flush=True))
+        sv["workload"] = ("Poisson arrivals, 1-32 images per request, 9 networks "
+                          "(32/64/128 px x M/N 0.10/0.25/0.50), BF16, 2 streams, HIP graphs; "
+                          f"{args.serve_requests} measured requests per load after 1000 warm-up")
+        out["serving"] = sv
     print(json.dumps(out))
 
 

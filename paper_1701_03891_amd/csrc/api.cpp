@@ -155,12 +155,14 @@ struct Layout {
 // Paper path: ypad fp32 [B][Mpad], xt [B][N] T, a1 [B][64][N] T, a2 [B][32][N] T
 //   (+ z3 fp32 [B][N] when training).
 // Generic path: xt and a_l [B][C_l][N] in compute precision (+ y64 for FP64).
+int rnd32(int v) { return (v + 31) / 32 * 32; }
+
 Layout layout(const dsi_net &n, int B, int train) {
   Layout L;
   size_t off = 0;
   if (n.prec == DSI_FP8_E4M3) {
     const size_t N = (size_t)n.N;
-    L.ypad = off; off += rnd((size_t)B * n.Mpad);
+    L.ypad = off; off += rnd((size_t)rnd32(B) * n.Mpad);  // y as e4m3 fragments
     L.xt = off; off += rnd((size_t)B * N * 2);
     L.act[1] = off; off += rnd((size_t)B * 64 * N);
     L.act[2] = off; off += rnd((size_t)B * 32 * N * 2);
@@ -170,7 +172,9 @@ Layout layout(const dsi_net &n, int B, int train) {
     return L;
   }
   const size_t N = (size_t)n.N, es = n.es;
-  L.ypad = off; off += rnd((size_t)B * n.Mpad * (n.prec == DSI_F64 ? 8 : 4));
+  // fp32/fp64 rows [B][Mpad], or (BF16) y as bf16 fragments of 32 rows
+  L.ypad = off;
+  off += rnd(std::max((size_t)B * n.Mpad * (n.prec == DSI_F64 ? 8 : 4), (size_t)rnd32(B) * n.Mpad * 2));
   L.xt = off; off += rnd((size_t)B * N * es);
   for (int l = 1; l <= n.d.L; ++l) {
     L.act[l] = off;
@@ -258,7 +262,7 @@ dsi_status pack_params_fp8(dsi_net *n, const dsi_params *p, hipStream_t s) {
   if ((st = device_amax(n, p->w[1], wcount(d, 1), s, &a_2)) != DSI_OK) return st;
   n->w_scale_fc = pow2_scale(a_fc);
   n->w_scale_2 = pow2_scale(a_2);
-  HIPCHK(dsi::pack_fc_fp8(p->w_fc, (u8 *)n->wfc, N, d.M, n->Mpad, 1.0f / n->w_scale_fc, s));
+  HIPCHK(dsi::pack_frag_fp8(p->w_fc, d.M, N, d.M, rnd32(N), n->Mpad, 1.0f / n->w_scale_fc, (u8 *)n->wfc, s));
   HIPCHK(dsi::pack_first(p->w[0], n->wp1, 64, 0, 1, s));
   HIPCHK(dsi::pack_mid_fp8(p->w[1], (u8 *)n->wp2, 1.0f / n->w_scale_2, s));
   HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, 1, s));
@@ -287,7 +291,10 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with
   }
   if (n->prec == DSI_FP8_E4M3) return pack_params_fp8(n, p, s);
   if (with_fc) {
-    HIPCHK(dsi::pack_fc(p->w_fc, n->wfc, N, d.M, n->Mpad, pr, s));
+    if (pr)  // fragment order for the proxy GEMM
+      HIPCHK(dsi::pack_frag_bf16(p->w_fc, d.M, N, d.M, rnd32(N), n->Mpad, (bf16 *)n->wfc, s));
+    else
+      HIPCHK(dsi::pack_fc(p->w_fc, n->wfc, N, d.M, n->Mpad, pr, s));
     if (n->wfcT) {
       (void)hipFree(n->wfcT);
       n->wfcT = nullptr;
@@ -344,7 +351,7 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     return DSI_OK;
   }
   // proxy x~ = W_fc y (K padded to Mpad with zeros)
-  const bool direct_y = ((M % 16 == 0) && aligned16(y)) || n->prec == DSI_FP8_E4M3;
+  const bool direct_y = ((M % 16 == 0) && aligned16(y)) || n->prec == DSI_FP8_E4M3 || n->prec == DSI_BF16;
   const float *yk = y;
   long ldy = M;
   if (!direct_y) {
@@ -374,8 +381,8 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     const float sy = n->act_scale[0], sa1 = n->act_scale[2];
     u8 *yq = at<u8>(base, L.ypad), *a1 = at<u8>(base, L.act[1]);
     bf16 *xt = at<bf16>(base, L.xt), *a2 = at<bf16>(base, L.act[2]);
-    HIPCHK(dsi::quant_rows(y, yq, B, M, n->Mpad, 1.0f / sy, s));
-    HIPCHK(dsi::gemm_nt_fp8(yq, n->Mpad, (const u8 *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, n->w_scale_fc * sy, s));
+    HIPCHK(dsi::pack_frag_fp8(y, M, B, M, rnd32(B), n->Mpad, 1.0f / sy, yq, s));
+    HIPCHK(dsi::gemm_frag_fp8(yq, (const u8 *)n->wfc, xt, N, B, N, n->Mpad / 64, n->w_scale_fc * sy, s));
     clk.mark();
     HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, u8>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
                                                                nullptr, a1, B, H, W, s, 1.0f / sa1)));
@@ -388,7 +395,9 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     clk.mark();
   } else if (n->prec == DSI_BF16) {
     bf16 *xt = at<bf16>(base, L.xt), *a1 = at<bf16>(base, L.act[1]), *a2 = at<bf16>(base, L.act[2]);
-    HIPCHK(dsi::gemm_nt_bf16_out_bf16(yk, ldy, (const bf16 *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
+    bf16 *yp = at<bf16>(base, L.ypad);
+    HIPCHK(dsi::pack_frag_bf16(y, M, B, M, rnd32(B), n->Mpad, yp, s));
+    HIPCHK(dsi::gemm_frag_bf16(yp, (const bf16 *)n->wfc, xt, N, B, N, n->Mpad / 16, s));
     clk.mark();
     HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, bf16>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
                                                                nullptr, a1, B, H, W, s)));
@@ -668,7 +677,8 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
   for (int q = 0; q <= DSI_MAX_LAYERS; ++q) n->act_scale[q] = 1.0f;
   const dsi_net_desc &d = *desc;
   auto A = [&](void **p, size_t bytes) { return st == DSI_OK ? (st = alloc(p, bytes)) : st; };
-  A(&n->wfc, (size_t)n->N * n->Mpad * n->es);
+  // BF16 / FP8: W_fc in fragment order, rows padded to a multiple of 32
+  A(&n->wfc, (size_t)(prec == DSI_BF16 || prec == DSI_FP8_E4M3 ? rnd32(n->N) : n->N) * n->Mpad * n->es);
   if (n->path == PATH_GENERIC) {
     for (int l = 0; l < d.L; ++l) {
       A(&n->w[l], wcount(d, l) * n->es);
@@ -744,8 +754,8 @@ dsi_status dsi_net_calibrate(dsi_ctx *ctx, dsi_net *net, const float *y, int B, 
   const float sy = pow2_scale(ay);
   u8 *yq = at<u8>(ctx->ws, L.ypad);
   bf16 *xt = at<bf16>(ctx->ws, L.xt), *a1 = at<bf16>(ctx->ws, L.end);
-  HIPCHK(dsi::quant_rows(y, yq, B, M, net->Mpad, 1.0f / sy, s));
-  HIPCHK(dsi::gemm_nt_fp8(yq, net->Mpad, (const u8 *)net->wfc, net->Mpad, xt, N, B, N, net->Mpad, net->w_scale_fc * sy, s));
+  HIPCHK(dsi::pack_frag_fp8(y, M, B, M, rnd32(B), net->Mpad, 1.0f / sy, yq, s));
+  HIPCHK(dsi::gemm_frag_fp8(yq, (const u8 *)net->wfc, xt, N, B, N, net->Mpad / 64, net->w_scale_fc * sy, s));
   HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, bf16>(xt, (const bf16 *)net->wp1, net->bp[0], d.bias_per_pixel,
                                                                 1, nullptr, a1, B, H, W, s)));
   HIPCHK(dsi::amax_bf16(a1, (long)B * 64 * N, net->amax_dev, s));
@@ -839,31 +849,12 @@ dsi_status check_grads(const dsi_net *net, const dsi_grads *g) {
 
 dsi_status ensure_wfcT(dsi_net *n, hipStream_t s) {
   if (n->wfcT || n->prec == DSI_F64) return DSI_OK;
-  // W_fc^T [M][N] fp32 from the packed copy [N][Mpad] (bf16 or fp32), via a host round trip
-  const size_t N = n->N, M = n->d.M, Mp = n->Mpad;
-  std::string host_in(N * Mp * n->es, '\0');
-  HIPCHK(hipStreamSynchronize(s));
-  HIPCHK(hipMemcpy(&host_in[0], n->wfc, host_in.size(), hipMemcpyDeviceToHost));
-  std::string host_out(N * M * 4, '\0');
-  float *o = reinterpret_cast<float *>(&host_out[0]);
-  for (size_t p = 0; p < N; ++p)
-    for (size_t m = 0; m < M; ++m) {
-      float v;
-      if (n->es == 2) {
-        uint16_t h;
-        memcpy(&h, &host_in[(p * Mp + m) * 2], 2);
-        uint32_t u = (uint32_t)h << 16;
-        memcpy(&v, &u, 4);
-      } else {
-        memcpy(&v, &host_in[(p * Mp + m) * 4], 4);
-      }
-      o[m * N + p] = v;
-    }
+  // W_fc^T [M][N] fp32 from the net's copy of W_fc (bf16 fragments or fp32 rows)
   void *dst = nullptr;
-  dsi_status st = alloc(&dst, host_out.size());
+  dsi_status st = alloc(&dst, (size_t)n->N * n->d.M * 4);
   if (st != DSI_OK) return st;
-  HIPCHK(hipMemcpy(dst, host_out.data(), host_out.size(), hipMemcpyHostToDevice));
   n->wfcT = (float *)dst;
+  HIPCHK(dsi::fc_transpose(n->wfc, n->prec == DSI_BF16, n->N, n->d.M, n->Mpad, n->wfcT, s));
   return DSI_OK;
 }
 }  // namespace

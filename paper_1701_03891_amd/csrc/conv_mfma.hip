@@ -79,9 +79,9 @@ template <> DSI_INLINE void load4f<bf16>(const bf16 *src, float *o) {
 }
 
 // ------------------------------------------------------------------ LDS staging
-// Copies NU 16-byte units into LDS.  unit(idx, loff) returns the global address
-// of unit idx (nullptr: outside the image, zero-filled) and sets its LDS byte
-// offset.  A thread issues the loads of a whole batch of its units before it
+// Copies up to NU 16-byte units into LDS.  unit(idx, loff) returns the global
+// address of unit idx (nullptr with loff set: outside the image, zero-filled;
+// nullptr with loff untouched: no such unit) and sets its LDS byte offset.  A thread issues the loads of a whole batch of its units before it
 // stores any of them, so their HBM/L2 latencies overlap instead of adding up.
 // MAXB bounds the batch (registers held by the loads in flight).
 template <int NU, int NT, int MAXB = 16, typename F>
@@ -148,10 +148,12 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   for (int cs = 0; cs < NCS; ++cs) {
     __syncthreads();  // previous slice fully consumed
     const T *src = in + (long)(img * NCS + cs) * H * W * SC;
-    // consecutive threads take consecutive 16-byte chunks of a pixel row (coalesced)
+    // 16 consecutive threads store 16 consecutive pixels of one chunk plane (no LDS bank
+    // conflicts); a wave reads whole pixels, so its global reads stay contiguous
     // (wider types keep fewer loads in flight: their weight fragments need the registers)
-    stage_units<LH * LW * CH16, NT, sizeof(T) == 2 ? 16 : 2>(lds, tid, [&](int idx, int &loff) -> const void * {
-      const int chunk = idx % CH16, pix = idx / CH16;
+    stage_units<(LH * LW + 15) / 16 * 16 * CH16, NT, sizeof(T) == 2 ? 16 : 2>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int chunk = (idx >> 4) % CH16, pix = (idx / (16 * CH16)) * 16 + (idx & 15);
+      if (pix >= LH * LW) return nullptr;
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
       loff = (row * CH16 + chunk) * PLANE + col * 16;
@@ -258,7 +260,10 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   constexpr int LWA = LW + 8;  // zero columns so the 8-wide reads of the last lanes stay in the tile
   constexpr int NCT = COUT / 32;
   constexpr bool WREG = sizeof(T) == 2;  // weights resident in registers
-  __shared__ __attribute__((aligned(16))) T tile[FIRST_IMGS * LH * LWA];
+  // 2-byte types keep a second copy shifted by one element, so every 8-element read
+  // starts on a 4-byte boundary (LDS reads at 2-byte offsets stall)
+  constexpr int NCOPY = sizeof(T) == 2 ? 2 : 1;
+  __shared__ __attribute__((aligned(16))) T tile[NCOPY * FIRST_IMGS * LH * LWA];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
   const int grp = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int img0 = grp * ipb, nimg = min(ipb, B - img0);
@@ -284,7 +289,16 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
 #pragma unroll
       for (int j = 0; j < BATCH; ++j) {
         const int idx = tid + (b0 + j) * 256;
-        if (b0 + j < NIT && idx < ne) tile[idx] = from_f32<T>(v[j]);
+        if (b0 + j < NIT && idx < ne) {
+          const T e = from_f32<T>(v[j]);
+          tile[idx] = e;
+          if constexpr (NCOPY == 2) {
+            // shifted copy: element col lands at col - 1; the row's last slot stays finite (0)
+            const int col = idx % LWA;
+            if (col > 0) tile[NE + idx - 1] = e;
+            if (col == LWA - 1) tile[NE + idx] = from_f32<T>(0.0f);
+          }
+        }
       }
     }
   }
@@ -333,12 +347,23 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
-    const T *trow = tile + (im * LH + wave) * LWA + px + 8 * h;
+    // odd start column: read the shifted copy one element earlier (4-byte aligned)
+    const int a0 = px + 8 * h, odd = NCOPY == 2 ? (a0 & 1) : 0;
+    const T *trow = tile + odd * (FIRST_IMGS * LH * LWA) + (im * LH + wave) * LWA + a0 - odd;
+    // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e.  2-byte
+    // types read each fragment as four 32-bit words (a 16-byte LDS read off a 16-byte
+    // boundary stalls), all 11 issued before the MFMAs
+    uint32_t xw[KT][sizeof(Frag8<T>) / 4];
 #pragma unroll
     for (int u = 0; u < KT; ++u) {
-      // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e (unaligned)
+      const uint32_t *p32 = reinterpret_cast<const uint32_t *>(trow + u * LWA);
+#pragma unroll
+      for (int q = 0; q < (int)(sizeof(Frag8<T>) / 4); ++q) xw[u][q] = p32[q];
+    }
+#pragma unroll
+    for (int u = 0; u < KT; ++u) {
       Frag8<T> xf;
-      __builtin_memcpy(&xf, trow + u * LWA, sizeof(xf));
+      __builtin_memcpy(&xf, xw[u], sizeof(xf));
       if (h) xf = frag_keep_first<T, 3>(xf);  // taps v >= 11 are padding: keep them finite-free
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
@@ -414,8 +439,9 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   for (int pass = 0; pass < NPASS; ++pass) {
     __syncthreads();
     // stage 16-byte units: unit q of pixel covers channels pass*CHL + q*EPU .. +EPU
-    stage_units<LH * LW * 4, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
-      const int q = idx % 4, pix = idx / 4;
+    stage_units<(LH * LW + 15) / 16 * 16 * 4, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int q = (idx >> 4) & 3, pix = (idx >> 6) * 16 + (idx & 15);
+      if (pix >= LH * LW) return nullptr;
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
       const int c0 = pass * CHL + q * EPU;
@@ -474,6 +500,45 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   }
 }
 
+// Value of lane n + S of the same 16-lane row (S > 0: DPP row_shl:S, S < 0:
+// row_shr:-S), zero where that lane falls outside the row.  S must fold to a
+// constant (the callers' loops are fully unrolled): DPP controls are immediates.
+DSI_INLINE int band_shift(int x, int S) {
+  switch (S) {
+    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x101, 0xf, 0xf, true);
+    case -1: return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);
+    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x102, 0xf, 0xf, true);
+    case -2: return __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);
+    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x103, 0xf, 0xf, true);
+    case -3: return __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, true);
+    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, true);
+    case -4: return __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);
+    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x105, 0xf, 0xf, true);
+    case -5: return __builtin_amdgcn_update_dpp(0, x, 0x115, 0xf, 0xf, true);
+    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x106, 0xf, 0xf, true);
+    case -6: return __builtin_amdgcn_update_dpp(0, x, 0x116, 0xf, 0xf, true);
+    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x107, 0xf, 0xf, true);
+    case -7: return __builtin_amdgcn_update_dpp(0, x, 0x117, 0xf, 0xf, true);
+    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x108, 0xf, 0xf, true);
+    case -8: return __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);
+    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x109, 0xf, 0xf, true);
+    case -9: return __builtin_amdgcn_update_dpp(0, x, 0x119, 0xf, 0xf, true);
+    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x10a, 0xf, 0xf, true);
+    case -10: return __builtin_amdgcn_update_dpp(0, x, 0x11a, 0xf, 0xf, true);
+    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x10b, 0xf, 0xf, true);
+    case -11: return __builtin_amdgcn_update_dpp(0, x, 0x11b, 0xf, 0xf, true);
+    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x10c, 0xf, 0xf, true);
+    case -12: return __builtin_amdgcn_update_dpp(0, x, 0x11c, 0xf, 0xf, true);
+    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x10d, 0xf, 0xf, true);
+    case -13: return __builtin_amdgcn_update_dpp(0, x, 0x11d, 0xf, 0xf, true);
+    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x10e, 0xf, 0xf, true);
+    case -14: return __builtin_amdgcn_update_dpp(0, x, 0x11e, 0xf, 0xf, true);
+    case 15: return __builtin_amdgcn_update_dpp(0, x, 0x10f, 0xf, 0xf, true);
+    case -15: return __builtin_amdgcn_update_dpp(0, x, 0x11f, 0xf, 0xf, true);
+    default: return x;
+  }
+}
+
 // BF16 variant: one 16-channel slice per pass and K = 32 packing two horizontal
 // taps (v = 2p, 2p + 1) x 16 channels, so a pass holds only 32 bytes per pixel
 // in LDS (62 KiB per block, two blocks per CU) and a tap pair costs one MFMA.
@@ -504,8 +569,9 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
   for (int sl = 0; sl < NS; ++sl) {
     __syncthreads();
     const bf16 *src = in + (long)(img * NS + sl) * H * W * 16;
-    stage_units<LH * LW * 2, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
-      const int q = idx & 1, pix = idx >> 1;
+    stage_units<(LH * LW + 15) / 16 * 16 * 2, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int q = (idx >> 4) & 1, pix = (idx >> 5) * 16 + (idx & 15);
+      if (pix >= LH * LW) return nullptr;
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
       loff = (row * 2 + q) * UNIT_PLANE + col * 16;
@@ -514,25 +580,26 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
     });
     __syncthreads();
     // Band operand of pair p at input row r: B[k][i] = W[c][u = r - i][v], zero outside
-    // 0 <= u <= 10; row r's band is row r-1's shifted by one lane within each 16-lane
-    // group (DPP row_shr:1, zero into lane 0), lane 0 taking W[u = r] while r <= 10.
-    i32x4 band[NP];
-#pragma unroll
-    for (int p = 0; p < NP; ++p) band[p] = i32x4{0, 0, 0, 0};
+    // 0 <= u <= 10.  It is one register z[p] moved across lanes: lane n of each 16-lane
+    // group holds W[u = 10 - n] (zero for n > 10), so B at row r is z shifted by 10 - r
+    // lanes (DPP row_shl:10-r for r < 10, row_shr:r-10 for r > 10, zeros shifted in).
+    i32x4 z[NP];
     const bf16 *whead = wl + (g >> 1) * KT * CIN + sl * 16 + 8 * (g & 1);
+#pragma unroll
+    for (int p = 0; p < NP; ++p) {
+      const i32x4 w = *reinterpret_cast<const i32x4 *>(whead + (2 * p * KT + KT - 1 - min(n, KT - 1)) * CIN);
+      z[p] = n < KT ? w : i32x4{0, 0, 0, 0};
+    }
 #pragma unroll
     for (int r = 0; r < LH; ++r) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
+        i32x4 band;
 #pragma unroll
-        for (int q = 0; q < 4; ++q) band[p][q] = __builtin_amdgcn_update_dpp(0, band[p][q], 0x111, 0xf, 0xf, true);
-        if (r < KT) {
-          const i32x4 head = *reinterpret_cast<const i32x4 *>(whead + (2 * p * KT + r) * CIN);
-          if (n == 0) band[p] = head;
-        }
+        for (int q = 0; q < 4; ++q) band[q] = band_shift(z[p][q], KT - 1 - r);
         Frag8<bf16> a, b;
         a.v = *reinterpret_cast<const bf16x8 *>(abase + r * 2 * UNIT_PLANE + 2 * p * 16);
-        __builtin_memcpy(&b, &band[p], 16);
+        __builtin_memcpy(&b, &band, 16);
         acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[p], 0, 0, 0);
       }
     }

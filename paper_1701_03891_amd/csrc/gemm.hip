@@ -179,6 +179,67 @@ hipError_t gemm_nt_fp8(const u8 *X, long ldx, const u8 *W, long ldw, bf16 *C, lo
   return hipGetLastError();
 }
 
+// Fragment-ordered operands (see pack_frag_*): a wave owns the 32 x 32 tile
+// (bt, ot) and its k-step ks reads the contiguous fragments Xp[bt][ks] and
+// Wp[ot][ks] (64 lanes x FE elements each), so every load instruction is one
+// coalesced 1 KiB (bf16) or 2 KiB (FP8) run.  PF k-steps are kept in flight.
+template <typename T>
+__global__ __launch_bounds__(256) void gemm_frag_kernel(const T *__restrict__ Xp, const T *__restrict__ Wp,
+                                                        bf16 *__restrict__ C, long ldc, int Bn, int O, int KS,
+                                                        float scale) {
+  constexpr int FE = sizeof(T) == 1 ? 32 : 8;
+  constexpr int PF = sizeof(T) == 1 ? 4 : 8;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int bt = blockIdx.y * 2 + (wave >> 1), ot = blockIdx.x * 2 + (wave & 1);
+  if (bt * 32 >= Bn || ot * 32 >= O) return;
+  const T *px = Xp + ((long)bt * KS * 64 + lane) * FE;
+  const T *pw = Wp + ((long)ot * KS * 64 + lane) * FE;
+  f32x16 acc;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
+  Frag8<T> fx[PF], fw[PF];
+#pragma unroll
+  for (int p = 0; p < PF; ++p)
+    if (p < KS) {
+      fx[p] = frag_load<T>(px + (long)p * 64 * FE);
+      fw[p] = frag_load<T>(pw + (long)p * 64 * FE);
+    }
+  for (int k = 0; k < KS; k += PF) {
+#pragma unroll
+    for (int p = 0; p < PF; ++p) {
+      if (k + p < KS) {
+        fx[p].mma(fw[p], acc);
+        const int kn = k + p + PF;
+        if (kn < KS) {
+          fx[p] = frag_load<T>(px + (long)kn * 64 * FE);
+          fw[p] = frag_load<T>(pw + (long)kn * 64 * FE);
+        }
+      }
+    }
+  }
+  const int o = ot * 32 + (lane & 31);
+  if (o >= O) return;
+#pragma unroll
+  for (int r = 0; r < 16; ++r) {
+    const int b = bt * 32 + mfma_row(lane, r);
+    if (b < Bn) C[(long)b * ldc + o] = (bf16)(acc[r] * scale);
+  }
+}
+
+hipError_t gemm_frag_bf16(const bf16 *Xp, const bf16 *Wp, bf16 *C, long ldc, int Bn, int O, int KS, hipStream_t s) {
+  if (Bn <= 0 || O <= 0) return hipSuccess;
+  dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
+  gemm_frag_kernel<bf16><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, 1.0f);
+  return hipGetLastError();
+}
+hipError_t gemm_frag_fp8(const u8 *Xp, const u8 *Wp, bf16 *C, long ldc, int Bn, int O, int KS, float scale,
+                         hipStream_t s) {
+  if (Bn <= 0 || O <= 0) return hipSuccess;
+  dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
+  gemm_frag_kernel<u8><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, scale);
+  return hipGetLastError();
+}
+
 // FP64 reference-precision variant (VALU), for the DSI_F64 checking path.
 __global__ __launch_bounds__(256) void gemm_nt_f64_kernel(const double *__restrict__ X, long ldx,
                                                           const double *__restrict__ W, long ldw,

@@ -99,6 +99,15 @@ hipError_t gemm_nt_fp8(const unsigned char *X, long ldx, const unsigned char *W,
 hipError_t amax_f32(const float *x, long n, unsigned *out, hipStream_t s);
 hipError_t amax_bf16(const __bf16 *x, long n, unsigned *out, hipStream_t s);
 hipError_t quant_rows(const float *in, unsigned char *out, int B, int M, int Mpad, float inv_scale, hipStream_t s);
+hipError_t pack_frag_bf16(const float *z, long ld, int R, int K, int Rp, int Kp, __bf16 *out, hipStream_t s);
+hipError_t pack_frag_fp8(const float *z, long ld, int R, int K, int Rp, int Kp, float inv_scale, unsigned char *out,
+                         hipStream_t s);
+hipError_t fc_transpose(const void *w, int frag, int N, int M, int Mpad, float *wT, hipStream_t s);
+// C[b][o] = scale * sum_k X[b][k] W[o][k], both operands in MFMA fragment order (pack_frag_*),
+// KS k-steps; C [Bn][ldc] bf16
+hipError_t gemm_frag_bf16(const __bf16 *Xp, const __bf16 *Wp, __bf16 *C, long ldc, int Bn, int O, int KS, hipStream_t s);
+hipError_t gemm_frag_fp8(const unsigned char *Xp, const unsigned char *Wp, __bf16 *C, long ldc, int Bn, int O, int KS,
+                         float scale, hipStream_t s);
 hipError_t pack_mid_fp8(const float *w, unsigned char *out, float inv_scale, hipStream_t s);
 hipError_t pack_fc_fp8(const float *w, unsigned char *out, int N, int M, int Mpad, float inv_scale, hipStream_t s);
 }  // namespace dsi

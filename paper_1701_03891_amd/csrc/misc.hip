@@ -177,6 +177,63 @@ hipError_t amax_bf16(const bf16 *x, long n, unsigned *out, hipStream_t s) {
   return hipGetLastError();
 }
 
+// ------------------------------------------------------- MFMA fragment order
+// Z [R][K] fp32 (row stride ld) -> the order a 32x32 MFMA consumes it in: for row
+// tile rt (32 rows), k-step ks (2 FE elements) and lane l, the FE elements
+//     Z[32 rt + l%32][2 FE ks + FE (l/32) + e],  e < FE,
+// scaled by `scale`, zero beyond R or K.  A wave then reads one fragment as one
+// contiguous 64 * FE-element run.  Rp (multiple of 32) and Kp (multiple of 2 FE)
+// are the padded extents.  FE = 8: bf16 (RNE); FE = 32: FP8 e4m3 codes.
+template <typename TD, int FE>
+__global__ void pack_frag_kernel(const float *__restrict__ z, long ld, int R, int K, int Rp, int Kp, float scale,
+                                 TD *__restrict__ out) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)Rp * Kp) return;
+  const int e = (int)(idx % FE);
+  long q = idx / FE;
+  const int l = (int)(q % 64);
+  q /= 64;
+  const int KS = Kp / (2 * FE);
+  const int ks = (int)(q % KS), rt = (int)(q / KS);
+  const int r = rt * 32 + (l & 31), k = ks * 2 * FE + FE * (l >> 5) + e;
+  const float v = (r < R && k < K) ? z[(long)r * ld + k] * scale : 0.0f;
+  if constexpr (FE == 8) out[idx] = from_f32<bf16>(v);
+  else out[idx] = f32_to_e4m3(v);
+}
+hipError_t pack_frag_bf16(const float *z, long ld, int R, int K, int Rp, int Kp, bf16 *out, hipStream_t s) {
+  const long n = (long)Rp * Kp;
+  if (n > 0) pack_frag_kernel<bf16, 8><<<GRID1(n), 0, s>>>(z, ld, R, K, Rp, Kp, 1.0f, out);
+  return hipGetLastError();
+}
+hipError_t pack_frag_fp8(const float *z, long ld, int R, int K, int Rp, int Kp, float inv_scale, u8 *out,
+                         hipStream_t s) {
+  const long n = (long)Rp * Kp;
+  if (n > 0) pack_frag_kernel<u8, 32><<<GRID1(n), 0, s>>>(z, ld, R, K, Rp, Kp, inv_scale, out);
+  return hipGetLastError();
+}
+
+// W_fc^T [M][N] fp32 from the net's copy of W_fc: fragment-ordered bf16 (frag = 1,
+// k-steps of 16 over Mpad) or row-major fp32 [N][Mpad] (frag = 0)
+__global__ void fc_transpose_kernel(const void *__restrict__ w, int frag, int N, int M, int Mpad,
+                                    float *__restrict__ wT) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)N * M) return;
+  const int m = (int)(idx / N), p = (int)(idx % N);
+  float v;
+  if (frag) {
+    const long q = (((long)(p >> 5) * (Mpad / 16) + m / 16) * 64 + (p & 31) + 32 * ((m & 15) >> 3)) * 8 + (m & 7);
+    v = (float)reinterpret_cast<const bf16 *>(w)[q];
+  } else {
+    v = reinterpret_cast<const float *>(w)[(long)p * Mpad + m];
+  }
+  wT[idx] = v;
+}
+hipError_t fc_transpose(const void *w, int frag, int N, int M, int Mpad, float *wT, hipStream_t s) {
+  const long n = (long)N * M;
+  if (n > 0) fc_transpose_kernel<<<GRID1(n), 0, s>>>(w, frag, N, M, Mpad, wT);
+  return hipGetLastError();
+}
+
 // rows [B][M] fp32 -> FP8 codes [B][Mpad] of in * inv_scale, zero-padded
 __global__ void quant_rows_kernel(const float *__restrict__ in, u8 *__restrict__ out, int B, int M, int Mpad,
                                   float inv_scale) {

@@ -168,6 +168,7 @@ class Server:
         self.in_flight: list[Batch] = []
         self.batches: list[Batch] = []
         self.max_concurrent = 0
+        self.n_finished = 0
         smallest = [executor.batch_bytes(k, self.buckets[0]) for k in range(n_nets)]
         for k, b in enumerate(smallest):
             if b > self.adm.budget:
@@ -211,6 +212,7 @@ class Server:
                     p.req.done_images += p.count
                     if p.req.done_images == p.req.n:
                         p.req.finish = t
+                        self.n_finished += 1
                 self.in_flight.remove(b)
                 self.free_slots.append(b.slot)
                 self.adm.give(b.nbytes)
@@ -225,6 +227,7 @@ class Server:
         for r in requests:
             r.arrival += start
         total = len(requests)
+        self.n_finished = 0
         finished = 0
         while finished < total:
             now = self.ex.now()
@@ -233,7 +236,7 @@ class Server:
             progressed = self._poll()
             while self._try_launch():
                 progressed = True
-            finished = sum(1 for r in requests if r.finish is not None)
+            finished = self.n_finished
             if not progressed and finished < total:
                 nxt = arrivals[0][0] + start if arrivals else None
                 self.ex.idle(nxt)
@@ -412,19 +415,45 @@ def make_requests(nets, phis, n_req, qps, max_images=32, cfg_id=7, device="cuda:
 
 def run_serving(n_req=2000, qps=2000.0, slots=2, budget_gib=16.0, buckets=DEFAULT_BUCKETS, warmup=200,
                 sizes=(32, 64, 128), ratios=(0.10, 0.25, 0.50)):
+    """One load point: `warmup` unmeasured requests, then n_req measured ones at `qps`."""
+    return sweep_serving((qps,), n_req, slots, budget_gib, buckets, warmup, sizes, ratios,
+                         at_fraction=None)["points"][0]
+
+
+def sweep_serving(qps_list, n_req=10000, slots=2, budget_gib=16.0, buckets=DEFAULT_BUCKETS, warmup=1000,
+                  sizes=(32, 64, 128), ratios=(0.10, 0.25, 0.50), at_fraction=0.7, log=None):
+    """Latency and throughput over offered loads.  Saturation is the delivered image
+    rate at the highest offered load (offered above capacity, the server delivers its
+    capacity); with at_fraction set, one more point runs at that fraction of it."""
     import torch
     nets, phis = make_workload(sizes, ratios)
     ex = GraphExecutor(nets, n_slots=slots, buckets=buckets)
     budget = int(budget_gib * (1 << 30))
-    # warm-up requests (not measured), then the measured run on a fresh server
-    Server(ex, len(nets), buckets, budget).run(make_requests(nets, phis, warmup, qps, cfg_id=8))
-    reqs = make_requests(nets, phis, n_req, qps)
-    srv = Server(ex, len(nets), buckets, budget)
-    stats = srv.run(reqs)
-    torch.cuda.synchronize()
-    stats.update({"qps": qps, "slots": slots, "budget_bytes": budget, "nets": len(nets)})
+    Server(ex, len(nets), buckets, budget).run(make_requests(nets, phis, warmup, max(qps_list), cfg_id=8))
+
+    def point(qps, cfg_id=7):
+        reqs = make_requests(nets, phis, n_req, qps, cfg_id=cfg_id)
+        st = Server(ex, len(nets), buckets, budget).run(reqs)
+        torch.cuda.synchronize()
+        st.update({"qps": qps, "slots": slots, "budget_bytes": budget, "nets": len(nets)})
+        del reqs
+        if log:
+            log(f"serving: {qps:.0f} req/s offered -> {st['images_per_s']:.0f} images/s, "
+                f"p50 {st['p50_ms']:.2f} ms, p99 {st['p99_ms']:.2f} ms")
+        return st
+
+    pts = [point(q) for q in qps_list]
+    out = {"points": pts}
+    if at_fraction is not None:
+        top = max(pts, key=lambda p: p["qps"])
+        sat_img = top["images_per_s"]
+        img_per_req = top["images"] / top["requests"]
+        q = at_fraction * sat_img / img_per_req
+        out["saturation_images_per_s"] = sat_img
+        out["at_fraction"] = at_fraction
+        out["at_fraction_point"] = point(q, cfg_id=9)
     ex.close()
-    return stats
+    return out
 
 
 if __name__ == "__main__":
