@@ -175,7 +175,7 @@ def c1_leg(ctx, P, torch, steps, warmup):
     return out, {"phi": phi, "x": x, "y": y.cpu().numpy().astype(np.float64)}
 
 
-def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=1e-3, pool=1024):
+def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=3e-4, pool=4096):
     """Adam training of the network (Sec. 4: MSE loss, backpropagation) on a pool of
     synthetic piecewise-smooth 64x64 images (a different seed from the benchmark
     batch), BF16 compute with FP32 master weights, through dsi_train_step.
@@ -282,7 +282,7 @@ def main():
     ap.add_argument("--cpu-images", type=int, default=256, help="images in the oracle's timed sample")
     ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle leg")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving (latency under load) leg")
-    ap.add_argument("--train-steps", type=int, default=400,
+    ap.add_argument("--train-steps", type=int, default=2000,
                     help="Adam steps on synthetic images before timing (0: He-init weights)")
     ap.add_argument("--serve-requests", type=int, default=10000, help="measured requests per load point")
     ap.add_argument("--serve-qps", type=str, default="2000,8000,64000",

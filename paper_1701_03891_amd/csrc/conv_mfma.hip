@@ -263,7 +263,10 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   // 2-byte types keep a second copy shifted by one element, so every 8-element read
   // starts on a 4-byte boundary (LDS reads at 2-byte offsets stall)
   constexpr int NCOPY = sizeof(T) == 2 ? 2 : 1;
-  __shared__ __attribute__((aligned(16))) T tile[NCOPY * FIRST_IMGS * LH * LWA];
+  // (the copies sit 64 bytes off a multiple of the bank width apart, so the even and odd
+  // lanes that read the same word index in the two copies use different banks)
+  constexpr int COPY = FIRST_IMGS * LH * LWA + (NCOPY == 2 ? 32 : 0);
+  __shared__ __attribute__((aligned(16))) T tile[NCOPY * COPY];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
   const int grp = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int img0 = grp * ipb, nimg = min(ipb, B - img0);
@@ -295,8 +298,8 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
           if constexpr (NCOPY == 2) {
             // shifted copy: element col lands at col - 1; the row's last slot stays finite (0)
             const int col = idx % LWA;
-            if (col > 0) tile[NE + idx - 1] = e;
-            if (col == LWA - 1) tile[NE + idx] = from_f32<T>(0.0f);
+            if (col > 0) tile[COPY + idx - 1] = e;
+            if (col == LWA - 1) tile[COPY + idx] = from_f32<T>(0.0f);
           }
         }
       }
@@ -349,7 +352,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
     // odd start column: read the shifted copy one element earlier (4-byte aligned)
     const int a0 = px + 8 * h, odd = NCOPY == 2 ? (a0 & 1) : 0;
-    const T *trow = tile + odd * (FIRST_IMGS * LH * LWA) + (im * LH + wave) * LWA + a0 - odd;
+    const T *trow = tile + odd * COPY + (im * LH + wave) * LWA + a0 - odd;
     // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e.  2-byte
     // types read each fragment as four 32-bit words (a 16-byte LDS read off a 16-byte
     // boundary stalls), all 11 issued before the MFMAs
@@ -553,9 +556,9 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
                                                              int tiles_per_img) {
   constexpr int TH = 16, TW = 64, LH = TH + 2 * RAD, LW = TW + 2 * RAD + 1;
   constexpr int NP = (KT + 1) / 2;          // tap pairs
-  constexpr int UNIT_PLANE = LW * 16;       // bytes between the two 8-channel planes of an LDS row
+  constexpr int ROWB = LW * 32;             // bytes per LDS row: pixels of two 8-channel units
   constexpr int NS = CIN / 16;              // 16-channel slices = passes
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * 2 * UNIT_PLANE];
+  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * ROWB];
   __shared__ __attribute__((aligned(16))) bf16 wl[(KT + 1) * KT * CIN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
   const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
@@ -565,16 +568,16 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
 #pragma unroll
   for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   // this lane's LDS column for tap pair 0 and its 8-channel plane
-  const unsigned char *abase = lds + (g & 1) * UNIT_PLANE + (wave * 16 + n + (g >> 1)) * 16;
+  const unsigned char *abase = lds + (g & 1) * 16 + (wave * 16 + n + (g >> 1)) * 32;
   for (int sl = 0; sl < NS; ++sl) {
     __syncthreads();
     const bf16 *src = in + (long)(img * NS + sl) * H * W * 16;
-    stage_units<(LH * LW + 15) / 16 * 16 * 2, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
-      const int q = (idx >> 4) & 1, pix = (idx >> 5) * 16 + (idx & 15);
-      if (pix >= LH * LW) return nullptr;
+    // unit idx = (pixel, 8-channel half) in LDS order: contiguous reads and stores
+    stage_units<LH * LW * 2, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
+      const int q = idx & 1, pix = idx >> 1;
       const int row = pix / LW, col = pix - row * LW;
       const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-      loff = (row * 2 + q) * UNIT_PLANE + col * 16;
+      loff = idx * 16;
       if (col >= LW - 1 || gi < 0 || gi >= H || gj < 0 || gj >= W) return nullptr;
       return src + ((long)gi * W + gj) * 16 + q * 8;
     });
@@ -598,7 +601,7 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
 #pragma unroll
         for (int q = 0; q < 4; ++q) band[q] = band_shift(z[p][q], KT - 1 - r);
         Frag8<bf16> a, b;
-        a.v = *reinterpret_cast<const bf16x8 *>(abase + r * 2 * UNIT_PLANE + 2 * p * 16);
+        a.v = *reinterpret_cast<const bf16x8 *>(abase + r * ROWB + 2 * p * 32);
         __builtin_memcpy(&b, &band, 16);
         acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[p], 0, 0, 0);
       }
