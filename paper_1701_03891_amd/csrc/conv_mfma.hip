@@ -249,6 +249,43 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
 // An FP8 output (TO = u8) is quantised as code = e4m3(oscale * value) into 64-channel slices.
 constexpr int FIRST_IMGS = 16;
 
+// Element-wise staging of conv_first's LDS tiles (any width, any input type): element
+// (image im, row, col) of the tile is input pixel (r0 + row, c0 + col), zero outside;
+// with two copies, the second holds each row shifted left by one element.
+template <typename T, typename TI, int LH, int LWA, int NCOPY, int COPY>
+DSI_INLINE void stage_first_scalar(T *tile, const TI *in, int tid, int nimg, int img0, int r0, int c0, int H, int W) {
+  constexpr int NE = FIRST_IMGS * LH * LWA, NIT = (NE + 255) / 256, BATCH = 16;
+  const int ne = nimg * LH * LWA;
+#pragma unroll
+  for (int b0 = 0; b0 < NIT; b0 += BATCH) {
+    float v[BATCH];
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j) {
+      const int idx = tid + (b0 + j) * 256;
+      v[j] = 0.0f;
+      if (b0 + j < NIT && idx < ne) {
+        const int im = idx / (LH * LWA), rem = idx - im * (LH * LWA);
+        const int row = rem / LWA, col = rem - row * LWA;
+        const int gi = r0 + row, gj = c0 + col;
+        if (gi >= 0 && gi < H && gj >= 0 && gj < W) v[j] = to_f32(in[((long)(img0 + im) * H + gi) * W + gj]);
+      }
+    }
+#pragma unroll
+    for (int j = 0; j < BATCH; ++j) {
+      const int idx = tid + (b0 + j) * 256;
+      if (b0 + j < NIT && idx < ne) {
+        const T e = from_f32<T>(v[j]);
+        tile[idx] = e;
+        if constexpr (NCOPY == 2) {
+          const int col = idx % LWA;
+          if (col > 0) tile[COPY + idx - 1] = e;
+          if (col == LWA - 1) tile[COPY + idx] = from_f32<T>(0.0f);
+        }
+      }
+    }
+  }
+}
+
 template <typename T, int COUT, int EPI, typename TI, typename TO>
 __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ in, const T *__restrict__ wp,
                                                          const float *__restrict__ bias, int bias_pp, int relu,
@@ -256,8 +293,10 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
                                                          int H, int W, int tiles_w, int tiles_per_img, int ipb,
                                                          float oscale) {
   constexpr int OSC = slice_ch<TO>();
-  constexpr int TH = 4, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
-  constexpr int LWA = LW + 8;  // zero columns so the 8-wide reads of the last lanes stay in the tile
+  constexpr int TH = 4, TW = 32, LH = TH + 2 * RAD;
+  // An LDS row holds input columns bj0 - 8 .. bj0 + 47 (OFF = 8 - RAD columns left of the
+  // first tap): 16-byte aligned for vector staging, and wide enough for every 8-wide read.
+  constexpr int OFF = 8 - RAD, LWA = 56, NVR = LWA / 8;
   constexpr int NCT = COUT / 32;
   constexpr bool WREG = sizeof(T) == 2;  // weights resident in registers
   // 2-byte types keep a second copy shifted by one element, so every 8-element read
@@ -271,39 +310,47 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   const int grp = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int img0 = grp * ipb, nimg = min(ipb, B - img0);
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  {
-    // element loads: a batch of 16 per thread in flight before their LDS stores
-    constexpr int NE = FIRST_IMGS * LH * LWA, NIT = (NE + 255) / 256, BATCH = 16;
-    const int ne = nimg * LH * LWA;
+  if constexpr (sizeof(TI) == 2 && sizeof(T) == 2) {
+    if (W % 8 == 0) {
+      // 16-byte vectors of 8 columns (all inside or all outside the image, as W % 8 == 0);
+      // the shifted copy's vector is this vector and the next one funnel-shifted by one
+      // element.  All loads of a thread are in flight before its LDS stores.
+      constexpr int NV = FIRST_IMGS * LH * NVR, NIT = (NV + 255) / 256;
+      const int nv = nimg * LH * NVR;
+      i32x4 v[NIT], w[NIT];
 #pragma unroll
-    for (int b0 = 0; b0 < NIT; b0 += BATCH) {
-      float v[BATCH];
-#pragma unroll
-      for (int j = 0; j < BATCH; ++j) {
-        const int idx = tid + (b0 + j) * 256;
-        v[j] = 0.0f;
-        if (b0 + j < NIT && idx < ne) {
-          const int im = idx / (LH * LWA), rem = idx - im * (LH * LWA);
-          const int row = rem / LWA, col = rem - row * LWA;
-          const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-          if (col < LW && gi >= 0 && gi < H && gj >= 0 && gj < W) v[j] = to_f32(in[((long)(img0 + im) * H + gi) * W + gj]);
-        }
-      }
-#pragma unroll
-      for (int j = 0; j < BATCH; ++j) {
-        const int idx = tid + (b0 + j) * 256;
-        if (b0 + j < NIT && idx < ne) {
-          const T e = from_f32<T>(v[j]);
-          tile[idx] = e;
-          if constexpr (NCOPY == 2) {
-            // shifted copy: element col lands at col - 1; the row's last slot stays finite (0)
-            const int col = idx % LWA;
-            if (col > 0) tile[COPY + idx - 1] = e;
-            if (col == LWA - 1) tile[COPY + idx] = from_f32<T>(0.0f);
+      for (int j = 0; j < NIT; ++j) {
+        const int idx = tid + j * 256;
+        v[j] = w[j] = i32x4{0, 0, 0, 0};
+        if (idx < nv) {
+          const int im = idx / (LH * NVR), rem = idx - im * (LH * NVR);
+          const int row = rem / NVR, vc = rem - row * NVR;
+          const int gi = bi0 - RAD + row, gj = bj0 - 8 + 8 * vc;
+          if (gi >= 0 && gi < H) {
+            const TI *src = in + ((long)(img0 + im) * H + gi) * W;
+            if (gj >= 0 && gj < W) v[j] = *reinterpret_cast<const i32x4 *>(src + gj);
+            if (vc + 1 < NVR && gj + 8 >= 0 && gj + 8 < W) w[j] = *reinterpret_cast<const i32x4 *>(src + gj + 8);
           }
         }
       }
+#pragma unroll
+      for (int j = 0; j < NIT; ++j) {
+        const int idx = tid + j * 256;
+        if (idx < nv) {
+          i32x4 sh;
+          sh[0] = (int)__builtin_amdgcn_alignbit((unsigned)v[j][1], (unsigned)v[j][0], 16);
+          sh[1] = (int)__builtin_amdgcn_alignbit((unsigned)v[j][2], (unsigned)v[j][1], 16);
+          sh[2] = (int)__builtin_amdgcn_alignbit((unsigned)v[j][3], (unsigned)v[j][2], 16);
+          sh[3] = (int)__builtin_amdgcn_alignbit((unsigned)w[j][0], (unsigned)v[j][3], 16);
+          *reinterpret_cast<i32x4 *>(tile + idx * 8) = v[j];
+          *reinterpret_cast<i32x4 *>(tile + COPY + idx * 8) = sh;
+        }
+      }
+    } else {
+      stage_first_scalar<T, TI, LH, LWA, NCOPY, COPY>(tile, in, tid, nimg, img0, bi0 - RAD, bj0 - 8, H, W);
     }
+  } else {
+    stage_first_scalar<T, TI, LH, LWA, NCOPY, COPY>(tile, in, tid, nimg, img0, bi0 - RAD, bj0 - 8, H, W);
   }
 
   const int gi = bi0 + wave, gj = bj0 + px;
@@ -351,7 +398,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
     // odd start column: read the shifted copy one element earlier (4-byte aligned)
-    const int a0 = px + 8 * h, odd = NCOPY == 2 ? (a0 & 1) : 0;
+    const int a0 = px + 8 * h + OFF, odd = NCOPY == 2 ? (a0 & 1) : 0;
     const T *trow = tile + odd * COPY + (im * LH + wave) * LWA + a0 - odd;
     // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e.  2-byte
     // types read each fragment as four 32-bit words (a 16-byte LDS read off a 16-byte
