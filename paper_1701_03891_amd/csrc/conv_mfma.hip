@@ -118,7 +118,12 @@ DSI_INLINE void stage_units(unsigned char *lds, int tid, F unit) {
 // oscale dequantises FP8 products (weight scale x activation scale); 1 otherwise.
 // A block has WAVES waves stacked vertically (WAVES * ROWS output rows x 32 columns).
 // The weight fragments of tap column v + 1 are loaded while tap column v computes.
-template <typename T, int CIN, int COUT, int ROWS, int WAVES, int EPI, typename TO>
+// ASYNC (BF16): two LDS slice buffers.  While slice cs computes, each thread loads its
+// units of slice cs+1, two per tap column right after that column's weight loads, and
+// stores them into the other buffer one column later, when they have long arrived
+// (loads retire in order, so no wait the compiler places reaches further back than a
+// column); one barrier per slice.
+template <typename T, int CIN, int COUT, int ROWS, int WAVES, int EPI, typename TO, bool ASYNC>
 __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restrict__ in, const T *__restrict__ wp,
                                                               const float *__restrict__ bias, int bias_pp, int relu,
                                                               const T *__restrict__ mask, TO *__restrict__ out,
@@ -131,7 +136,11 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   constexpr int FE = 16 * (CH16 / 2) / (int)sizeof(T);  // fragment elements per lane: 8, 8, 32
   constexpr int NCT = COUT / 32, NCS = CIN / SC;
   constexpr int PLANE = LW * 16;              // bytes between chunk planes of one LDS row
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * CH16 * PLANE];
+  static_assert(!ASYNC || sizeof(T) == 2, "prefetched staging is for 2-byte types");
+  constexpr int NU = LH * CH16 * LW;          // 16-byte units of one slice
+  constexpr int NPF = (NU + NT - 1) / NT;     // units per thread per slice
+  constexpr int BUF = NU * 16;                // bytes of one slice buffer
+  __shared__ __attribute__((aligned(16))) unsigned char lds[(ASYNC ? 2 : 1) * BUF];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
   const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
@@ -145,7 +154,33 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[i][c][r] = 0.0f;
 
+  // unit k of this thread (u = k NT + tid, [row][chunk][col] order) of slice sl, zero
+  // outside the image
+  auto unit_load = [&](int sl, int k) -> i32x4 {
+    const int u = k * NT + tid;
+    const int row = u / (CH16 * LW), rem = u - row * (CH16 * LW);
+    const int chunk = rem / LW, col = rem - chunk * LW;
+    const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+    i32x4 val = {0, 0, 0, 0};
+    if (k < NPF && u < NU && gi >= 0 && gi < H && gj >= 0 && gj < W)
+      val = *reinterpret_cast<const i32x4 *>(in + (long)(img * NCS + sl) * H * W * SC + ((long)gi * W + gj) * SC +
+                                             chunk * 8);
+    return val;
+  };
+  auto unit_store = [&](unsigned char *b, int k, const i32x4 &val) {
+    if (k < NPF && k * NT + tid < NU) *reinterpret_cast<i32x4 *>(b + (k * NT + tid) * 16) = val;
+  };
+  if constexpr (ASYNC) {
+    i32x4 pf[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) pf[k] = unit_load(0, k);
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) unit_store(lds, k, pf[k]);
+    __syncthreads();
+  }
+
   for (int cs = 0; cs < NCS; ++cs) {
+   if constexpr (!ASYNC) {
     __syncthreads();  // previous slice fully consumed
     const T *src = in + (long)(img * NCS + cs) * H * W * SC;
     // 16 consecutive threads store 16 consecutive pixels of one chunk plane (no LDS bank
@@ -161,12 +196,20 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
       return src + ((long)gi * W + gj) * SC + chunk * (16 / (int)sizeof(T));
     });
     __syncthreads();
+   }
+    const unsigned char *buf = lds + (ASYNC ? (cs & 1) * BUF : 0);
     const T *wcs = wp + (long)cs * KT * KT * NCT * 64 * FE + lane * FE;
     Frag8<T> wf[KT][NCT], wn[KT][NCT];
 #pragma unroll
     for (int u = 0; u < KT; ++u)
 #pragma unroll
       for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + (u * NCT + c) * 64 * FE);
+    unsigned char *nbuf = lds + ((cs + 1) & 1) * BUF;  // next slice's buffer (ASYNC), unread now
+    i32x4 pa0 = {0, 0, 0, 0}, pa1 = {0, 0, 0, 0};     // units loaded one column ago
+    int pk = -1;                                       // their first unit index
+    // (unrolled when prefetching: every load then sits in straight-line code, and the
+    // waits the compiler places for a column's weights count exactly the later loads)
+#pragma unroll (ASYNC ? KT : 1)
     for (int v = 0; v < KT; ++v) {
       if (v + 1 < KT) {
 #pragma unroll
@@ -174,7 +217,22 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
 #pragma unroll
           for (int c = 0; c < NCT; ++c) wn[u][c] = frag_load<T>(wcs + (((v + 1) * KT + u) * NCT + c) * 64 * FE);
       }
-      const unsigned char *lrow = lds + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + (px + v) * 16;
+      if constexpr (ASYNC) {
+        static_assert(NPF <= 2 * (KT - 1), "two units per column must cover the slice");
+        if (cs + 1 < NCS) {
+          if (pk >= 0) {
+            unit_store(nbuf, pk, pa0);
+            unit_store(nbuf, pk + 1, pa1);
+          }
+          pk = -1;
+          if (2 * v < NPF) {
+            pa0 = unit_load(cs + 1, 2 * v);
+            pa1 = unit_load(cs + 1, 2 * v + 1);
+            pk = 2 * v;
+          }
+        }
+      }
+      const unsigned char *lrow = buf + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + (px + v) * 16;
 #pragma unroll
       for (int rr = 0; rr < ROWS + 2 * RAD; ++rr) {
         Frag8<T> xf = lds_frag<T>(lrow + rr * CH16 * PLANE, PLANE);
@@ -191,6 +249,13 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
       for (int u = 0; u < KT; ++u)
 #pragma unroll
         for (int c = 0; c < NCT; ++c) wf[u][c] = wn[u][c];
+    }
+    if constexpr (ASYNC) {
+      if (cs + 1 < NCS && pk >= 0) {
+        unit_store(nbuf, pk, pa0);
+        unit_store(nbuf, pk + 1, pa1);
+      }
+      __syncthreads();  // the next slice is in place and every wave is done with this one
     }
   }
 
@@ -704,13 +769,15 @@ template <typename T, int CIN, int COUT, int EPI, typename TO>
 hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
                     TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
-  // BF16 with 32 outputs: 8 waves (two per SIMD) on a 64 x 32 tile; its 74-row halo
-  // slice (99 KiB of LDS) fits one block per CU.  Other types keep 4 waves.
+  // BF16 with 32 outputs: 4 waves x 8 rows on a 32 x 32 tile, two 56 KiB slice buffers,
+  // the next slice loaded into registers while this one computes.  Other types: 4 waves,
+  // one buffer.
   constexpr int ROWS = COUT == 32 ? 8 : 4;
-  constexpr int WAVES = (sizeof(T) == 2 && COUT == 32) ? 8 : 4;
+  constexpr int WAVES = 4;
+  constexpr bool ASYNC = sizeof(T) == 2 && COUT == 32;
   int tw, tpi;
   tiles(H, W, WAVES * ROWS, 32, tw, tpi);
-  conv_mid_kernel<T, CIN, COUT, ROWS, WAVES, EPI, TO>
+  conv_mid_kernel<T, CIN, COUT, ROWS, WAVES, EPI, TO, ASYNC>
       <<<B * tpi, 64 * WAVES, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
   return hipGetLastError();
 }
