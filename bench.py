@@ -175,6 +175,78 @@ def c1_leg(ctx, P, torch, steps, warmup):
     return out, {"phi": phi, "x": x, "y": y.cpu().numpy().astype(np.float64)}
 
 
+SWEEP_N = 32                                       # image side of the M/N sweep
+SWEEP_RATIOS = (0.01, 0.05, 0.10, 0.20, 0.25, 0.50)
+
+
+def sweep_leg(ctx, P, torch, n_test=2000, train_steps=2000, log=None):
+    """Recovery quality and run time over M/N (Sec. 5, Figs. 2-3 and Table 1 analogue) on
+    32 x 32 piecewise-smooth images: per ratio, a network trained from He-init (BF16,
+    Adam) on its own Phi, then success rate (phi, Sec. 5) and mean PSNR over n_test
+    fresh Monte Carlo images, and the recovery time per image."""
+    import synth
+    n = SWEEP_N
+    N = n * n
+    dev = "cuda:0"
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    pool = synth.piecewise_smooth_images(8192, n, n, cfg_id=30, stream=11).reshape(8192, -1)
+    xtest = synth.piecewise_smooth_images(n_test, n, n, cfg_id=31).reshape(n_test, -1)
+    xp_d, xt_d = t(pool), t(xtest)
+    out, data = {}, {}
+    for q, r in enumerate(SWEEP_RATIOS):
+        Mr = synth.m_for_ratio(r, N)
+        phi = synth.make_phi(Mr, N, cfg_id=40 + q)
+        prm = synth.he_init(synth.PAPER_ARCH, n, n, bias_per_pixel=True, cfg_id=40 + q)
+        params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+        phi_d = t(phi)
+        yp, yt = ctx.measure(phi_d, xp_d), ctx.measure(phi_d, xt_d)
+        net = ctx.prepare(n, n, Mr, params, prec="bf16")
+        net.reserve(256, train=True)
+        opt = P.AdamState.zeros_like(params)
+        g = synth.rng(40 + q, 12)
+        for st in range(train_steps):
+            idx = torch.tensor(g.choice(8192, size=128, replace=False), device=dev)
+            net.train_step(params, opt, yp[idx].contiguous(), xp_d[idx].contiguous(), lr=3e-4)
+        net.update(params)
+        xh = torch.empty((n_test, n, n), dtype=torch.float32, device=dev)
+        for b0 in range(0, n_test, 256):
+            net.recover(yt[b0:b0 + 256].contiguous(), xh[b0:b0 + 256])
+        m = ctx.metrics(xh.reshape(n_test, -1), xt_d).cpu().numpy()
+        ms1, _ = time_recover(net, yt[:1].contiguous(), n, n, 50, 5, torch)
+        ms256, _ = time_recover(net, yt[:256].contiguous(), n, n, 20, 3, torch)
+        out[f"{r:.2f}"] = {"M": Mr, "success_rate": float(m[:, 3].mean()), "psnr_mean_db": float(m[:, 1].mean()),
+                           "ms_per_image_batch1": ms1, "images_per_s_batch256": 256 / (ms256 / 1e3)}
+        if log:
+            log(f"sweep M/N {r:.2f}: success {m[:, 3].mean():.3f}, PSNR {m[:, 1].mean():.2f} dB, "
+                f"{ms1 * 1e3:.0f} us per image alone")
+        data[f"{r:.2f}"] = {"phi": phi, "y": yt[:16].cpu().numpy().astype(np.float64)}
+        net.free()
+    out["workload"] = (f"32x32 piecewise-smooth images, Gaussian Phi per ratio, network trained "
+                       f"{train_steps} Adam steps (lr 3e-4, batch 128) per ratio, {n_test} test images")
+    return out, {"x": xtest[:16], "ratios": data}
+
+
+def cpu_sweep(sw, n_img=16, threads=16):
+    """ISTA-DCT (the classical sparsity-regularised solver) on the first n_img test images
+    of every ratio of the sweep, images in parallel threads: success rate, PSNR, time."""
+    import oracle
+    from concurrent.futures import ThreadPoolExecutor
+    out = {}
+    x = sw["x"][:n_img]
+    for key, d in sw["ratios"].items():
+        def one(i):
+            t0 = time.perf_counter()
+            xi, _, _ = oracle.ista_dct(d["phi"], d["y"][i], SWEEP_N, SWEEP_N)
+            return xi, time.perf_counter() - t0
+        with ThreadPoolExecutor(max_workers=threads) as ex:
+            res = list(ex.map(one, range(n_img)))
+        xh = np.stack([r[0] for r in res])
+        out[key] = {"success_rate": float(oracle.success(xh, x).mean()),
+                    "psnr_mean_db": float(oracle.psnr(xh, x).mean()),
+                    "seconds_per_image": float(np.mean([r[1] for r in res])), "images": n_img}
+    return out
+
+
 def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=3e-4, pool=4096):
     """Adam training of the network (Sec. 4: MSE loss, backpropagation) on a pool of
     synthetic piecewise-smooth 64x64 images (a different seed from the benchmark
@@ -288,6 +360,9 @@ def main():
     ap.add_argument("--serve-qps", type=str, default="2000,8000,64000",
                     help="offered loads (requests/s); the highest should exceed capacity")
     ap.add_argument("--no-extra", action="store_true", help="skip the 128x128 FP8 and 32x32 legs")
+    ap.add_argument("--sweep", action="store_true",
+                    help="also run the M/N sweep (32x32: trained networks per ratio, 2000 test images, "
+                         "ISTA-DCT on 16 of them); adds a few minutes")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -326,6 +401,9 @@ def main():
         res[prec] = r
         net.free()
 
+    sw = sw_data = None
+    if args.sweep:
+        sw, sw_data = sweep_leg(ctx, P, torch, log=lambda m: print(m, file=sys.stderr, flush=True))
     c4 = c4_data = c1 = c1_data = None
     if not args.no_extra:
         c4, c4_data = c4_leg(ctx, P, torch, 20, 3)
@@ -374,6 +452,7 @@ def main():
         "training": train,
         "c4_128x128": c4,
         "c1_32x32": c1,
+        "sweep_mn": sw,
     }
     if not args.no_cpu:
         y_host = y.cpu().numpy().astype(np.float64)
@@ -381,6 +460,8 @@ def main():
                                c4=c4_data, c1=c1_data)
         out["cpu_baseline"] = cb
         out["accuracy_vs_fp64_on_sample"] = acc
+        if sw_data is not None:
+            out["sweep_mn_ista_dct"] = cpu_sweep(sw_data)
         if c1 is not None and "ista_dct" in cb:
             out["c1_32x32"]["ista_over_network_time_per_image"] = (
                 cb["ista_dct"]["seconds_per_image"] / (c1["batch8"]["us_per_image"] * 1e-6))
