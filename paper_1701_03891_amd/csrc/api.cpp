@@ -519,7 +519,11 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
   return DSI_OK;
 }
 
-int wgrad_chunks(int B) { return std::max(1, std::min(B, 16)); }
+// image chunks (blocks per (ci tile, tap column) pair) of the weight-gradient kernels:
+// the conv2 kernel has 22 such pairs and one block per CU fits, so 23 chunks make two
+// even rounds of 506 blocks on 256 CUs; the single-channel ones have 1-2 pairs
+int wgrad_chunks(int B) { return std::max(1, std::min(B, 23)); }
+int wgrad_thin_chunks(int B) { return std::max(1, std::min(B, 128)); }
 
 // Backward of the paper's network on the MFMA kernels.  gz3 = dL/dz3 fp32 [B][N].
 // Scratch: g2 (T, [B][2][N][16]), g1 (T, [B][4][N][16]), gxt fp32 [B][N], wgrad partials.
@@ -534,12 +538,16 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
   T *g2 = at<T>(scratch, off); off += rnd((size_t)B * 32 * N * sizeof(T));
   T *g1 = at<T>(scratch, off); off += rnd((size_t)B * 64 * N * sizeof(T));
   float *gxt = at<float>(scratch, off); off += rnd((size_t)B * N * 4);
+  // channel-major copies of g2 and a1 for the conv2 weight gradient (BF16, W % 8 == 0)
+  const bool planar = bf && W % 8 == 0;
+  bf16 *g2p = at<bf16>(scratch, off); off += planar ? rnd((size_t)B * 32 * N * 2) : 0;
+  bf16 *a1p = at<bf16>(scratch, off); off += planar ? rnd((size_t)B * 64 * N * 2) : 0;
   float *partial = at<float>(scratch, off);
-  const int nch = wgrad_chunks(B);
+  const int nch = wgrad_chunks(B), ncht = wgrad_thin_chunks(B);
   const ActView v1{1, H, W, 0}, v32{32, H, W, 1}, v64{64, H, W, 1};
   // layer 3: dW3, db3, then g2 = (a2 > 0) * dgrad(gz3)
   if constexpr (bf) {
-    HIPCHK(dsi::conv_wgrad_thin<float>(dsi::THIN_OUT, (const bf16 *)a2, gz3, 32, partial, nch, g->w[2], B, H, W, s));
+    HIPCHK(dsi::conv_wgrad_thin<float>(dsi::THIN_OUT, (const bf16 *)a2, gz3, 32, partial, ncht, g->w[2], B, H, W, s));
   } else {
     HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>(gz3, v1, (const float *)a2, v32, B, 11, g->w[2], s)));
   }
@@ -547,7 +555,13 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
   HIPCHK((dsi::conv_first<T, 32, dsi::EPI_MASK, float, T>(gz3, (const T *)n->wp3f, nullptr, 0, 0, a2, g2, B, H, W, s)));
   // layer 2: dW2, db2, then g1 = (a1 > 0) * dgrad(g2)
   if constexpr (bf) {
-    HIPCHK(dsi::conv_wgrad_mid((const bf16 *)g2, (const bf16 *)a1, 64, partial, nch, g->w[1], B, H, W, s));
+    if (planar) {
+      HIPCHK(dsi::to_planar((const bf16 *)g2, g2p, B, 32, N, s));
+      HIPCHK(dsi::to_planar((const bf16 *)a1, a1p, B, 64, N, s));
+      HIPCHK(dsi::conv_wgrad_mid(g2p, a1p, 64, partial, nch, g->w[1], B, H, W, s, true));
+    } else {
+      HIPCHK(dsi::conv_wgrad_mid((const bf16 *)g2, (const bf16 *)a1, 64, partial, nch, g->w[1], B, H, W, s));
+    }
   } else {
     HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>((const float *)g2, v32, (const float *)a1, v64, B, 11, g->w[1], s)));
   }
@@ -555,7 +569,7 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
   HIPCHK((dsi::conv_mid<T, 32, 64, dsi::EPI_MASK, T>(g2, (const T *)n->wp2f, nullptr, 0, 0, a1, g1, B, H, W, s)));
   // layer 1: dW1, db1
   if constexpr (bf) {
-    HIPCHK(dsi::conv_wgrad_thin<bf16>(dsi::THIN_IN, (const bf16 *)g1, (const bf16 *)xt, 64, partial, nch, g->w[0], B, H, W, s));
+    HIPCHK(dsi::conv_wgrad_thin<bf16>(dsi::THIN_IN, (const bf16 *)g1, (const bf16 *)xt, 64, partial, ncht, g->w[0], B, H, W, s));
   } else {
     HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>((const float *)g1, v64, (const float *)xt, v1, B, 11, g->w[0], s)));
   }
@@ -576,10 +590,11 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
 
 size_t backward_paper_scratch(const dsi_net &n, int B) {
   const size_t N = n.N, es = n.es;
-  const int nch = wgrad_chunks(B);
-  size_t part = std::max({dsi::conv_wgrad_mid_partial_floats(64, nch), dsi::conv_wgrad_thin_partial_floats(64, nch),
-                          dsi::conv_wgrad_thin_partial_floats(32, nch)});
-  return rnd(B * 32 * N * es) + rnd(B * 64 * N * es) + rnd(B * N * 4) + rnd(part * 4);
+  const int nch = wgrad_chunks(B), ncht = wgrad_thin_chunks(B);
+  size_t part = std::max({dsi::conv_wgrad_mid_partial_floats(64, nch), dsi::conv_wgrad_thin_partial_floats(64, ncht),
+                          dsi::conv_wgrad_thin_partial_floats(32, ncht)});
+  const size_t planar = (n.prec == DSI_BF16 && n.d.n2 % 8 == 0) ? rnd(B * 32 * N * 2) + rnd(B * 64 * N * 2) : 0;
+  return rnd(B * 32 * N * es) + rnd(B * 64 * N * es) + rnd(B * N * 4) + planar + rnd(part * 4);
 }
 
 size_t backward_scratch_bytes(const dsi_net &n, int B) {

@@ -9,8 +9,9 @@
 // four waves own four 16-column chunks.  Per strip of 8 output rows the block
 // stages G (8 rows) and A (18 rows) in LDS as planar [channel][row][col]
 // tiles; a wave keeps the 8 G fragments of the strip in registers and walks
-// the 18 A rows once, each A fragment (8 consecutive columns shifted by v - 5,
-// an unaligned 16-byte LDS read) feeding up to 8 MFMAs (one per u).
+// the 18 A rows once, each A fragment (8 consecutive columns shifted by v - 5:
+// the block stages its A strip already shifted by its tap column, so the read is
+// a 16-byte aligned LDS load) feeding up to 8 MFMAs (one per u).
 // Accumulators (11 u x 32 x 32) live across all strips and images of the
 // block; each block then writes its raw accumulators, and a second kernel sums
 // the partials in a fixed order (deterministic).
@@ -23,7 +24,7 @@ constexpr int WG_SR = 8;            // output rows per strip
 constexpr int WG_LR = WG_SR + 10;   // input rows per strip
 constexpr int WG_TW = 64;           // output columns per pass (4 waves x 16)
 constexpr int WG_GW = WG_TW + 8;    // G tile row pitch (elements)
-constexpr int WG_AW = WG_TW + 16;   // A tile row pitch: cols -5 .. 74 (+ padding)
+constexpr int WG_AW = WG_TW + 16;   // A tile row pitch (64 columns + padding)
 
 // g [B][2][H][W][16] (T), a [B][CIN/16][H][W][16] (T)
 // partial [(ct*11 + v)*nchunk + chunk][4 waves][11 u][64 lanes][16] fp32
@@ -35,8 +36,7 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restr
   __shared__ __attribute__((aligned(16))) bf16 al[32 * WG_LR * WG_AW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
   const int chunk = blockIdx.x % nchunk, v = (blockIdx.x / nchunk) % 11, ct = blockIdx.x / nchunk / 11;
-  const int per = (B + nchunk - 1) / nchunk;
-  const int b0 = chunk * per, b1 = min(B, b0 + per);
+  const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
 
   f32x16 acc[11];
 #pragma unroll
@@ -48,32 +48,62 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restr
     for (int i0 = 0; i0 < H; i0 += WG_SR)
       for (int j0 = 0; j0 < W; j0 += WG_TW) {
         __syncthreads();
-        // G strip: rows i0..i0+7, cols j0..j0+63, 32 channels (two 16-channel slices)
-        for (int idx = tid; idx < WG_SR * WG_TW * 4; idx += 256) {
-          const int q = idx & 3, pix = idx >> 2;               // q: 8-channel group
-          const int row = pix / WG_TW, col = pix - row * WG_TW;
-          const int gi = i0 + row, gj = j0 + col;
-          bf16x8 val;
-          if (gi < H && gj < W)
-            val = *reinterpret_cast<const bf16x8 *>(g + ((((long)b * 2 + (q >> 1)) * H + gi) * W + gj) * 16 + (q & 1) * 8);
-          else
-            for (int e = 0; e < 8; ++e) val[e] = (bf16)0.0f;
+        // G strip: rows i0..i0+7, cols j0..j0+63, 32 channels (two 16-channel slices);
+        // A strip: rows i0-5..i0+12, cols j0-5..j0+68, channels ct*32..ct*32+31.
+        // Every load of a thread is issued before its (transposing) LDS stores.
+        constexpr int NG = WG_SR * WG_TW * 4, NA = WG_LR * WG_TW * 4;
+        constexpr int IG = (NG + 255) / 256, IA = (NA + 255) / 256, BA = 8;
+        {
+          i32x4 gv[IG];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) gl[((q * 8 + e) * WG_SR + row) * WG_GW + col] = val[e];
+          for (int it = 0; it < IG; ++it) {
+            const int idx = tid + it * 256;
+            const int q = idx & 3, pix = idx >> 2;               // q: 8-channel group
+            const int row = pix / WG_TW, col = pix - row * WG_TW;
+            const int gi = i0 + row, gj = j0 + col;
+            gv[it] = i32x4{0, 0, 0, 0};
+            if (idx < NG && gi < H && gj < W)
+              gv[it] = *reinterpret_cast<const i32x4 *>(g + ((((long)b * 2 + (q >> 1)) * H + gi) * W + gj) * 16 + (q & 1) * 8);
+          }
+#pragma unroll
+          for (int it = 0; it < IG; ++it) {
+            const int idx = tid + it * 256;
+            const int q = idx & 3, pix = idx >> 2;
+            const int row = pix / WG_TW, col = pix - row * WG_TW;
+            if (idx < NG) {
+              bf16x8 e8;
+              __builtin_memcpy(&e8, &gv[it], 16);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) gl[((q * 8 + e) * WG_SR + row) * WG_GW + col] = e8[e];
+            }
+          }
         }
-        // A strip: rows i0-5..i0+12, cols j0-5..j0+68, channels ct*32..ct*32+31
-        for (int idx = tid; idx < WG_LR * (WG_TW + 10) * 4; idx += 256) {
-          const int q = idx & 3, pix = idx >> 2;
-          const int row = pix / (WG_TW + 10), col = pix - row * (WG_TW + 10);
-          const int gi = i0 - 5 + row, gj = j0 - 5 + col;
-          const int c0 = ct * 32 + q * 8;
-          bf16x8 val;
-          if (gi >= 0 && gi < H && gj >= 0 && gj < W)
-            val = *reinterpret_cast<const bf16x8 *>(a + ((((long)b * (CIN / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
-          else
-            for (int e = 0; e < 8; ++e) val[e] = (bf16)0.0f;
+#pragma unroll 1
+        for (int i0a = 0; i0a < IA; i0a += BA) {
+          i32x4 av[BA];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) al[((q * 8 + e) * WG_LR + row) * WG_AW + col] = val[e];
+          for (int j = 0; j < BA; ++j) {
+            const int idx = tid + (i0a + j) * 256;
+            const int q = idx & 3, pix = idx >> 2;
+            const int row = pix / WG_TW, col = pix - row * WG_TW;
+            const int gi = i0 - 5 + row, gj = j0 + v - 5 + col;
+            const int c0 = ct * 32 + q * 8;
+            av[j] = i32x4{0, 0, 0, 0};
+            if (i0a + j < IA && idx < NA && gi >= 0 && gi < H && gj >= 0 && gj < W)
+              av[j] = *reinterpret_cast<const i32x4 *>(a + ((((long)b * (CIN / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
+          }
+#pragma unroll
+          for (int j = 0; j < BA; ++j) {
+            const int idx = tid + (i0a + j) * 256;
+            const int q = idx & 3, pix = idx >> 2;
+            const int row = pix / WG_TW, col = pix - row * WG_TW;
+            if (i0a + j < IA && idx < NA) {
+              bf16x8 e8;
+              __builtin_memcpy(&e8, &av[j], 16);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) al[((q * 8 + e) * WG_LR + row) * WG_AW + col] = e8[e];
+            }
+          }
         }
         __syncthreads();
         // G fragments of the strip: lane (co = c32, h) holds G[co][i][16w + 8h + e]
@@ -81,12 +111,13 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restr
 #pragma unroll
         for (int i = 0; i < WG_SR; ++i)
           gf[i].v = *reinterpret_cast<const bf16x8 *>(gl + (c32 * WG_SR + i) * WG_GW + 16 * wave + 8 * h);
-        // walk the input rows: A[ci][r][16w + 8h + e + v] (LDS col; col 0 = global j0 - 5)
-        const bf16 *arow = al + (c32 * WG_LR) * WG_AW + 16 * wave + 8 * h + v;
+        // walk the input rows: A[ci][r][j0 + 16w + 8h + e + v - 5] (LDS col 0 = global j0 + v - 5,
+        // so each fragment read is a 16-byte aligned LDS load)
+        const bf16 *arow = al + (c32 * WG_LR) * WG_AW + 16 * wave + 8 * h;
 #pragma unroll
         for (int r = 0; r < WG_LR; ++r) {
           Frag8<bf16> af;
-          __builtin_memcpy(&af.v, arow + r * WG_AW, 16);
+          af.v = *reinterpret_cast<const bf16x8 *>(arow + r * WG_AW);
 #pragma unroll
           for (int u = 0; u < 11; ++u) {
             const int i = r - u;
@@ -102,36 +133,226 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restr
       *reinterpret_cast<f32x4 *>(dst + (u * 64 + lane) * 16 + r) = f32x4{acc[u][r], acc[u][r + 1], acc[u][r + 2], acc[u][r + 3]};
 }
 
-// dW[co][ci][u][v] = sum over chunks and waves of the partials (fixed order).
-__global__ void conv_wgrad_mid_reduce_kernel(const float *__restrict__ partial, float *__restrict__ dw, int CIN,
-                                             int nchunk) {
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (long)32 * CIN * 121) return;
-  const int v = (int)(idx % 11), u = (int)(idx / 11 % 11), ci = (int)(idx / 121 % CIN), co = (int)(idx / 121 / CIN);
-  const int ct = ci >> 5;
-  const int lane = 32 * ((co & 7) >> 2) + (ci & 31), r = 4 * (co >> 3) + (co & 3);
+// ------------------------------------------------------------------------
+// Channel-major copies for the conv2 weight gradient: x [B][C/16][HW][16] ->
+// [B][C][HW].  A block transposes 16 channels x 64 pixels through LDS, so both the
+// reads (64 pixels x 32 bytes) and the writes (16 rows of 128 bytes) are contiguous.
+__global__ __launch_bounds__(256) void to_planar_kernel(const bf16 *__restrict__ in, bf16 *__restrict__ out, int C,
+                                                        int HW) {
+  __shared__ bf16 t[16][64 + 2];
+  const int nchunk = (HW + 63) / 64;
+  const int chunk = blockIdx.x % nchunk, cs = (blockIdx.x / nchunk) % (C / 16), b = blockIdx.x / nchunk / (C / 16);
+  const int p0 = chunk * 64, tid = threadIdx.x;
+  {
+    const int p = tid >> 2, q = tid & 3;   // pixel, 4-channel quarter
+    bf16x4 v;
+    for (int e = 0; e < 4; ++e) v[e] = (bf16)0.0f;
+    if (p0 + p < HW) v = *reinterpret_cast<const bf16x4 *>(in + (((long)b * (C / 16) + cs) * HW + p0 + p) * 16 + 4 * q);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) t[4 * q + e][p] = v[e];
+  }
+  __syncthreads();
+  const int c = tid >> 4, k = tid & 15;    // channel, 4-pixel group
+  const int p = p0 + 4 * k;
+  bf16 *dst = out + ((long)b * C + cs * 16 + c) * HW + p;
+  if (p + 3 < HW) {
+    bf16x4 v;
+#pragma unroll
+    for (int e = 0; e < 4; ++e) v[e] = t[c][4 * k + e];
+    *reinterpret_cast<bf16x4 *>(dst) = v;
+  } else {
+    for (int e = 0; e < 4 && p + e < HW; ++e) dst[e] = t[c][4 * k + e];
+  }
+}
+
+hipError_t to_planar(const bf16 *in, bf16 *out, int B, int C, int HW, hipStream_t s) {
+  if (B <= 0) return hipSuccess;
+  const long blocks = (long)B * (C / 16) * ((HW + 63) / 64);
+  to_planar_kernel<<<(unsigned)blocks, 256, 0, s>>>(in, out, C, HW);
+  return hipGetLastError();
+}
+
+// 8 consecutive bf16 starting S elements into the 16 of (lo, hi)
+template <int S> DSI_INLINE i32x4 window8(const i32x4 &lo, const i32x4 &hi) {
+  const unsigned d[8] = {(unsigned)lo[0], (unsigned)lo[1], (unsigned)lo[2], (unsigned)lo[3],
+                         (unsigned)hi[0], (unsigned)hi[1], (unsigned)hi[2], (unsigned)hi[3]};
+  i32x4 r;
+#pragma unroll
+  for (int i = 0; i < 4; ++i)
+    r[i] = (S & 1) ? (int)__builtin_amdgcn_alignbit(d[i + S / 2 + 1], d[i + S / 2], 16) : (int)d[i + S / 2];
+  return r;
+}
+DSI_INLINE i32x4 window8(const i32x4 &lo, const i32x4 &hi, int s) {
+  switch (s) {  // s is uniform across the block
+    case 0: return window8<0>(lo, hi);
+    case 1: return window8<1>(lo, hi);
+    case 2: return window8<2>(lo, hi);
+    case 3: return window8<3>(lo, hi);
+    case 4: return window8<4>(lo, hi);
+    case 5: return window8<5>(lo, hi);
+    case 6: return window8<6>(lo, hi);
+    default: return window8<7>(lo, hi);
+  }
+}
+
+// conv2 weight gradient from channel-major g [B][32][H][W] and a [B][CIN][H][W]
+// (W % 8 == 0): the same blocks, strips and MFMA walk as conv_wgrad_mid_kernel, but the
+// strips are staged with 16-byte vector loads and stores (8 columns of one channel);
+// the A strip is shifted by the block's v - 5 through a funnel of two aligned vectors.
+template <int CIN>
+__global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *__restrict__ g,
+                                                                    const bf16 *__restrict__ a,
+                                                                    float *__restrict__ partial, int B, int H, int W,
+                                                                    int nchunk) {
+  // LDS tiles [channel][row][64 cols], each channel's tile padded to 16 bytes past a
+  // multiple of 256: the 32 lanes of a half-wave read 32 channels of the same (row,
+  // col), which then fall on distinct banks
+  constexpr int GS = WG_SR * WG_TW + 8, AS = WG_LR * WG_TW + 8;   // channel strides (elements)
+  __shared__ __attribute__((aligned(16))) bf16 gl[32 * GS];
+  __shared__ __attribute__((aligned(16))) bf16 al[32 * AS];
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
+  const int chunk = blockIdx.x % nchunk, v = (blockIdx.x / nchunk) % 11, ct = blockIdx.x / nchunk / 11;
+  const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
+  const int sh = (v + 3) & 7;   // (v - 5) mod 8: offset of the A window in its aligned vectors
+
+  f32x16 acc[11];
+#pragma unroll
+  for (int u = 0; u < 11; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; ++r) acc[u][r] = 0.0f;
+
+  // one A unit (channel c, row, 8-column group k): the window of two aligned vectors
+  auto a_load = [&](int b, int i0, int j0, int idx, i32x4 &lo, i32x4 &hi) {
+    const int c = idx / (WG_LR * 8), rem = idx - c * (WG_LR * 8), row = rem >> 3, k = rem & 7;
+    const int gi = i0 - 5 + row, base = j0 + v - 5 + 8 * k - sh;   // aligned
+    lo = hi = i32x4{0, 0, 0, 0};
+    if (gi >= 0 && gi < H) {
+      const bf16 *src = a + (((long)b * CIN + ct * 32 + c) * H + gi) * W;
+      if (base >= 0 && base < W) lo = *reinterpret_cast<const i32x4 *>(src + base);
+      if (base + 8 >= 0 && base + 8 < W) hi = *reinterpret_cast<const i32x4 *>(src + base + 8);
+    }
+  };
+  auto a_store = [&](int idx, const i32x4 &lo, const i32x4 &hi) {
+    const int c = idx / (WG_LR * 8), rem = idx - c * (WG_LR * 8), row = rem >> 3, k = rem & 7;
+    *reinterpret_cast<i32x4 *>(al + c * AS + row * WG_TW + 8 * k) = window8(lo, hi, sh);
+  };
+
+  for (int b = b0; b < b1; ++b)
+    for (int i0 = 0; i0 < H; i0 += WG_SR)
+      for (int j0 = 0; j0 < W; j0 += WG_TW) {
+        __syncthreads();
+        // two round trips per strip: G and the first half of A, then the rest of A
+        constexpr int IG = 32 * WG_SR * 8 / 256, IA = 32 * WG_LR * 8 / 256, IA1 = IA / 2;
+        static_assert(32 * WG_LR * 8 % 256 == 0 && IA % 2 == 0, "A units split evenly");
+        {
+          i32x4 gv[IG], lo[IA1], hi[IA1];
+#pragma unroll
+          for (int it = 0; it < IG; ++it) {
+            const int idx = tid + it * 256;
+            const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
+            const int gi = i0 + row, gj = j0 + 8 * k;
+            gv[it] = i32x4{0, 0, 0, 0};
+            if (gi < H && gj < W) gv[it] = *reinterpret_cast<const i32x4 *>(g + (((long)b * 32 + c) * H + gi) * W + gj);
+          }
+#pragma unroll
+          for (int j = 0; j < IA1; ++j) a_load(b, i0, j0, tid + j * 256, lo[j], hi[j]);
+#pragma unroll
+          for (int it = 0; it < IG; ++it) {
+            const int idx = tid + it * 256;
+            const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
+            *reinterpret_cast<i32x4 *>(gl + c * GS + row * WG_TW + 8 * k) = gv[it];
+          }
+#pragma unroll
+          for (int j = 0; j < IA1; ++j) a_store(tid + j * 256, lo[j], hi[j]);
+        }
+        {
+          i32x4 lo[IA - IA1], hi[IA - IA1];
+#pragma unroll
+          for (int j = 0; j < IA - IA1; ++j) a_load(b, i0, j0, tid + (IA1 + j) * 256, lo[j], hi[j]);
+#pragma unroll
+          for (int j = 0; j < IA - IA1; ++j) a_store(tid + (IA1 + j) * 256, lo[j], hi[j]);
+        }
+        __syncthreads();
+        Frag8<bf16> gf[WG_SR];
+#pragma unroll
+        for (int i = 0; i < WG_SR; ++i)
+          gf[i].v = *reinterpret_cast<const bf16x8 *>(gl + c32 * GS + i * WG_TW + 16 * wave + 8 * h);
+        const bf16 *arow = al + c32 * AS + 16 * wave + 8 * h;
+#pragma unroll
+        for (int r = 0; r < WG_LR; ++r) {
+          Frag8<bf16> af;
+          af.v = *reinterpret_cast<const bf16x8 *>(arow + r * WG_TW);
+#pragma unroll
+          for (int u = 0; u < 11; ++u) {
+            const int i = r - u;
+            if (i >= 0 && i < WG_SR) gf[i].mma(af, acc[u]);
+          }
+        }
+      }
+  float *dst = partial + ((long)blockIdx.x * 4 + wave) * 11 * 64 * 16;
+#pragma unroll
+  for (int u = 0; u < 11; ++u)
+#pragma unroll
+    for (int r = 0; r < 16; r += 4)
+      *reinterpret_cast<f32x4 *>(dst + (u * 64 + lane) * 16 + r) = f32x4{acc[u][r], acc[u][r + 1], acc[u][r + 2], acc[u][r + 3]};
+}
+
+// Partial-sum reduction: a block owns RED_SLOTS consecutive accumulator slots; its
+// RED_PARTS thread groups each sum every RED_PARTS-th partial of a slot in order, and
+// the group sums are added in group order, so the result is the same on every run.
+constexpr int RED_SLOTS = 32, RED_PARTS = 8;
+DSI_INLINE float reduce_parts(float s) {
+  __shared__ float red[RED_PARTS][RED_SLOTS];
+  const int slot = threadIdx.x % RED_SLOTS, part = threadIdx.x / RED_SLOTS;
+  red[part][slot] = s;
+  __syncthreads();
+  float t = 0.0f;
+  if (part == 0)
+    for (int q = 0; q < RED_PARTS; ++q) t += red[q][slot];
+  return t;
+}
+
+// dW[co][ci][u][v] = sum over chunks and waves of the partials (fixed order).  Slots
+// (u, lane, r) of one (ci tile, tap column) group are consecutive partials.
+__global__ __launch_bounds__(256) void conv_wgrad_mid_reduce_kernel(const float *__restrict__ partial,
+                                                                    float *__restrict__ dw, int CIN, int nchunk) {
+  const long idx = (long)blockIdx.x * RED_SLOTS + (threadIdx.x % RED_SLOTS);
+  const int part = threadIdx.x / RED_SLOTS;
+  const long nslot = (long)(CIN / 32) * 11 * 11 * 64 * 16;
+  const int slot = (int)(idx % (11 * 64 * 16));       // (u, lane, r)
+  const int grp = (int)(idx / (11 * 64 * 16));        // ct * 11 + v
   float s = 0.0f;
-  for (int c = 0; c < nchunk; ++c)
-    for (int w = 0; w < 4; ++w)
-      s += partial[((((long)(ct * 11 + v) * nchunk + c) * 4 + w) * 11 + u) * 64 * 16 + lane * 16 + r];
-  dw[idx] = s;
+  if (idx < nslot) {
+    const float *p = partial + (long)grp * nchunk * 4 * 11 * 64 * 16 + slot;
+    for (int cw = part; cw < nchunk * 4; cw += RED_PARTS) s += p[(long)cw * 11 * 64 * 16];
+  }
+  s = reduce_parts(s);
+  if (part != 0 || idx >= nslot) return;
+  const int u = slot / 1024, lane = (slot / 16) & 63, r = slot & 15;
+  const int v = grp % 11, ct = grp / 11;
+  const int co = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), ci = ct * 32 + (lane & 31);
+  dw[(((long)co * CIN + ci) * 11 + u) * 11 + v] = s;
 }
 
 size_t conv_wgrad_mid_partial_floats(int CIN, int nchunk) { return (size_t)(CIN / 32) * 11 * nchunk * 4 * 11 * 64 * 16; }
 
 hipError_t conv_wgrad_mid(const bf16 *g, const bf16 *a, int CIN, float *partial, int nchunk, float *dw, int B,
-                          int H, int W, hipStream_t s) {
+                          int H, int W, hipStream_t s, bool planar) {
   const int blocks = (CIN / 32) * 11 * nchunk;
-  if (CIN == 64)
+  if (planar && W % 8 != 0) return hipErrorInvalidValue;
+  if (CIN == 64 && planar)
+    conv_wgrad_mid_planar_kernel<64><<<blocks, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
+  else if (CIN == 64)
     conv_wgrad_mid_kernel<64><<<blocks, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
-  else if (CIN == 32)
+  else if (CIN == 32 && !planar)
     conv_wgrad_mid_kernel<32><<<blocks, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
   else
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long n = (long)32 * CIN * 121;
-  conv_wgrad_mid_reduce_kernel<<<(unsigned)((n + 255) / 256), 256, 0, s>>>(partial, dw, CIN, nchunk);
+  const long n = (long)(CIN / 32) * 11 * 11 * 64 * 16;
+  conv_wgrad_mid_reduce_kernel<<<(unsigned)((n + RED_SLOTS - 1) / RED_SLOTS), RED_SLOTS * RED_PARTS, 0, s>>>(
+      partial, dw, CIN, nchunk);
   return hipGetLastError();
 }
 
@@ -146,8 +367,9 @@ namespace dsi {
 //   THIN_OUT (layer 3): D_u[ci][v] = sum_{i,j'} a[ci][i+u-5][j'] * g[i][j'-v+5]
 //   THIN_IN  (layer 1): D_u[co][v] = sum_{i,j}  g[co][i][j]      * x[i+u-5][j+v-5]
 // M = wide channel (32 per tile), N = tap column v (11 of 32 used), K = 16
-// columns; the thin operand is a Toeplitz band read with unaligned 16-byte
-// LDS loads.  Layout and reduction as in conv_wgrad_mid_kernel.
+// columns; the thin operand is a Toeplitz band read as four 32-bit LDS words from
+// one of two copies of its tile (the other shifted by one element).  Layout and
+// reduction as in conv_wgrad_mid_kernel.
 constexpr int TG_PITCH = WG_TW + 16;  // thin tile pitch: cols -5 .. 74 (+ padding)
 
 // wide [B][CW/16][H][W][16] (bf16); thin [B][H][W] (TT, converted to bf16)
@@ -159,11 +381,22 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
   constexpr int WR = MODE == THIN_OUT ? WG_LR : WG_SR;   // wide rows per strip
   constexpr int TR = MODE == THIN_OUT ? WG_SR : WG_LR;   // thin rows per strip
   __shared__ __attribute__((aligned(16))) bf16 wl[32 * WR * WG_GW];
-  __shared__ __attribute__((aligned(16))) bf16 tl[TR * TG_PITCH];
+  // the thin tile twice: as staged, and shifted left by one element, so every 8-wide
+  // read can start on a 4-byte boundary (LDS reads at 2-byte offsets stall); the
+  // second copy sits 64 bytes off a multiple of the bank width from the first
+  constexpr int TCOPY = TR * TG_PITCH + 32;
+  __shared__ __attribute__((aligned(16))) bf16 tl[2 * TCOPY];
+  auto thin_frag = [&](int row, int start) {
+    const int odd = start & 1;
+    const uint32_t *p = reinterpret_cast<const uint32_t *>(tl + odd * TCOPY + row * TG_PITCH + start - odd);
+    uint32_t w4[4] = {p[0], p[1], p[2], p[3]};
+    Frag8<bf16> f;
+    __builtin_memcpy(&f.v, w4, 16);
+    return f;
+  };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
   const int chunk = blockIdx.x % nchunk, ct = blockIdx.x / nchunk;
-  const int per = (B + nchunk - 1) / nchunk;
-  const int b0 = chunk * per, b1 = min(B, b0 + per);
+  const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
   const int wrow0 = MODE == THIN_OUT ? -5 : 0, trow0 = MODE == THIN_OUT ? 0 : -5;
 
   f32x16 acc[11];
@@ -176,25 +409,59 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
     for (int i0 = 0; i0 < H; i0 += WG_SR)
       for (int j0 = 0; j0 < W; j0 += WG_TW) {
         __syncthreads();
-        for (int idx = tid; idx < WR * WG_TW * 4; idx += 256) {
-          const int q = idx & 3, pix = idx >> 2;
-          const int row = pix / WG_TW, col = pix - row * WG_TW;
-          const int gi = i0 + wrow0 + row, gj = j0 + col;
-          const int c0 = ct * 32 + q * 8;
-          bf16x8 val;
-          if (gi >= 0 && gi < H && gj < W)
-            val = *reinterpret_cast<const bf16x8 *>(wide + ((((long)b * (CW / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
-          else
-            for (int e = 0; e < 8; ++e) val[e] = (bf16)0.0f;
+        // wide strip (32 channels, transposed to planar) and thin strip; every load of a
+        // thread is issued before its LDS stores
+        constexpr int NWU = WR * WG_TW * 4, NTU = TR * TG_PITCH;
+        constexpr int IW = (NWU + 255) / 256, IT = (NTU + 255) / 256, BW = 8;
+#pragma unroll 1
+        for (int i0w = 0; i0w < IW; i0w += BW) {
+          i32x4 wv[BW];
 #pragma unroll
-          for (int e = 0; e < 8; ++e) wl[((q * 8 + e) * WR + row) * WG_GW + col] = val[e];
+          for (int j = 0; j < BW; ++j) {
+            const int idx = tid + (i0w + j) * 256;
+            const int q = idx & 3, pix = idx >> 2;
+            const int row = pix / WG_TW, col = pix - row * WG_TW;
+            const int gi = i0 + wrow0 + row, gj = j0 + col;
+            const int c0 = ct * 32 + q * 8;
+            wv[j] = i32x4{0, 0, 0, 0};
+            if (i0w + j < IW && idx < NWU && gi >= 0 && gi < H && gj < W)
+              wv[j] = *reinterpret_cast<const i32x4 *>(wide + ((((long)b * (CW / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
+          }
+#pragma unroll
+          for (int j = 0; j < BW; ++j) {
+            const int idx = tid + (i0w + j) * 256;
+            const int q = idx & 3, pix = idx >> 2;
+            const int row = pix / WG_TW, col = pix - row * WG_TW;
+            if (i0w + j < IW && idx < NWU) {
+              bf16x8 e8;
+              __builtin_memcpy(&e8, &wv[j], 16);
+#pragma unroll
+              for (int e = 0; e < 8; ++e) wl[((q * 8 + e) * WR + row) * WG_GW + col] = e8[e];
+            }
+          }
         }
-        for (int idx = tid; idx < TR * TG_PITCH; idx += 256) {
-          const int row = idx / TG_PITCH, col = idx - row * TG_PITCH;
-          const int gi = i0 + trow0 + row, gj = j0 - 5 + col;
-          float val = 0.0f;
-          if (gi >= 0 && gi < H && gj >= 0 && gj < W && col < WG_TW + 10) val = to_f32(thin[((long)b * H + gi) * W + gj]);
-          tl[idx] = (bf16)val;
+        {
+          float tv[IT];
+#pragma unroll
+          for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * 256;
+            const int row = idx / TG_PITCH, col = idx - row * TG_PITCH;
+            const int gi = i0 + trow0 + row, gj = j0 - 5 + col;
+            tv[it] = 0.0f;
+            if (idx < NTU && gi >= 0 && gi < H && gj >= 0 && gj < W && col < WG_TW + 10)
+              tv[it] = to_f32(thin[((long)b * H + gi) * W + gj]);
+          }
+#pragma unroll
+          for (int it = 0; it < IT; ++it) {
+            const int idx = tid + it * 256;
+            if (idx < NTU) {
+              const bf16 e = (bf16)tv[it];
+              const int col = idx % TG_PITCH;
+              tl[idx] = e;
+              if (col > 0) tl[TCOPY + idx - 1] = e;
+              if (col == TG_PITCH - 1) tl[TCOPY + idx] = (bf16)0.0f;
+            }
+          }
         }
         __syncthreads();
         const int j16 = 16 * wave + 8 * h;  // lane's 8 columns within the pass
@@ -204,7 +471,7 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
           Frag8<bf16> bf[WG_SR];
 #pragma unroll
           for (int i = 0; i < WG_SR; ++i) {
-            __builtin_memcpy(&bf[i].v, tl + i * TG_PITCH + j16 + 10 - vv, 16);
+            bf[i] = thin_frag(i, j16 + 10 - vv);
             if (c32 >= 11) bf[i] = frag_zero<bf16>();
           }
 #pragma unroll
@@ -226,7 +493,7 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
 #pragma unroll
           for (int r = 0; r < WG_LR; ++r) {
             Frag8<bf16> bfr;
-            __builtin_memcpy(&bfr.v, tl + r * TG_PITCH + j16 + vv, 16);
+            bfr = thin_frag(r, j16 + vv);
             if (c32 >= 11) bfr = frag_zero<bf16>();
 #pragma unroll
             for (int u = 0; u < 11; ++u) {
@@ -245,19 +512,25 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
 }
 
 // dW[m][u][v] (m = the wide channel; layer 3: [1][CW][11][11], layer 1: [CW][1][11][11]:
-// the same linear order) = sum over chunks and waves of the partials.
-__global__ void conv_wgrad_thin_reduce_kernel(const float *__restrict__ partial, float *__restrict__ dw, int CW,
-                                              int nchunk) {
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= CW * 121) return;
-  const int v = idx % 11, u = idx / 11 % 11, m = idx / 121;
-  const int ct = m >> 5, ml = m & 31;
-  const int lane = 32 * ((ml & 7) >> 2) + v, r = 4 * (ml >> 3) + (ml & 3);
+// the same linear order) = sum over chunks and waves of the partials (fixed order); a
+// thread owns one accumulator slot (u, lane, r) of one channel tile.
+__global__ __launch_bounds__(256) void conv_wgrad_thin_reduce_kernel(const float *__restrict__ partial,
+                                                                     float *__restrict__ dw, int CW, int nchunk) {
+  const int idx = blockIdx.x * RED_SLOTS + (threadIdx.x % RED_SLOTS);
+  const int part = threadIdx.x / RED_SLOTS;
+  const int nslot = (CW / 32) * 11 * 64 * 16;
+  const int slot = idx % (11 * 64 * 16), ct = idx / (11 * 64 * 16);
+  const int u = slot / 1024, lane = (slot / 16) & 63, r = slot & 15;
+  const int v = lane & 31;   // tap columns 11..31 of the band are padding
   float s = 0.0f;
-  for (int c = 0; c < nchunk; ++c)
-    for (int w = 0; w < 4; ++w)
-      s += partial[((((long)ct * nchunk + c) * 4 + w) * 11 + u) * 64 * 16 + lane * 16 + r];
-  dw[idx] = s;
+  if (idx < nslot && v < 11) {
+    const float *p = partial + (long)ct * nchunk * 4 * 11 * 64 * 16 + slot;
+    for (int cw = part; cw < nchunk * 4; cw += RED_PARTS) s += p[(long)cw * 11 * 64 * 16];
+  }
+  s = reduce_parts(s);
+  if (part != 0 || idx >= nslot || v >= 11) return;
+  const int m = ct * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  dw[((long)m * 11 + u) * 11 + v] = s;
 }
 
 size_t conv_wgrad_thin_partial_floats(int CW, int nchunk) { return (size_t)(CW / 32) * nchunk * 4 * 11 * 64 * 16; }
@@ -272,7 +545,8 @@ hipError_t conv_wgrad_thin(int mode, const bf16 *wide, const TT *thin, int CW, f
     conv_wgrad_thin_kernel<THIN_IN, TT><<<blocks, 256, 0, s>>>(wide, thin, CW, partial, B, H, W, nchunk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  conv_wgrad_thin_reduce_kernel<<<(CW * 121 + 255) / 256, 256, 0, s>>>(partial, dw, CW, nchunk);
+  conv_wgrad_thin_reduce_kernel<<<((CW / 32) * 11 * 64 * 16 + RED_SLOTS - 1) / RED_SLOTS, RED_SLOTS * RED_PARTS, 0,
+                                  s>>>(partial, dw, CW, nchunk);
   return hipGetLastError();
 }
 

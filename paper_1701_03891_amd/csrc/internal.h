@@ -85,7 +85,9 @@ namespace dsi {
 enum { THIN_OUT = 0, THIN_IN = 1 };
 size_t conv_wgrad_mid_partial_floats(int CIN, int nchunk);
 hipError_t conv_wgrad_mid(const __bf16 *g, const __bf16 *a, int CIN, float *partial, int nchunk, float *dw, int B,
-                          int H, int W, hipStream_t s);
+                          int H, int W, hipStream_t s, bool planar = false);
+// x [B][C/16][HW][16] -> [B][C][HW] (bf16), for the channel-major conv2 weight gradient
+hipError_t to_planar(const __bf16 *in, __bf16 *out, int B, int C, int HW, hipStream_t s);
 size_t conv_wgrad_thin_partial_floats(int CW, int nchunk);
 template <typename TT>
 hipError_t conv_wgrad_thin(int mode, const __bf16 *wide, const TT *thin, int CW, float *partial, int nchunk, float *dw,
