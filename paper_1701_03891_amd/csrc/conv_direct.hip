@@ -140,6 +140,63 @@ __global__ __launch_bounds__(256) void bias_grad_pc_kernel(const TG *__restrict_
   if (threadIdx.x == 0) db[co] = (TD)red[0];
 }
 
+// Per-pixel bias gradient over 16-byte units (EPU elements of TG): a block owns 16
+// consecutive units of an image's tensor; its 16 thread groups each sum every 16th
+// image of the batch, and the group sums are combined in group order (deterministic).
+// Units are read contiguously whatever the layout: blocked [C/16][HW][16] (a unit is
+// EPU channels of one pixel) or planar [C][HW] with HW % EPU == 0 (EPU pixels of one
+// channel).
+template <typename TG, typename TD>
+__global__ __launch_bounds__(256) void bias_grad_units_kernel(const TG *__restrict__ gz, ActView vg, int B,
+                                                              TD *__restrict__ db) {
+  constexpr int EPU = 16 / (int)sizeof(TG);
+  const int HW = vg.H * vg.W;
+  const long NU = (long)vg.C * HW / EPU;
+  const long u = (long)blockIdx.x * 16 + (threadIdx.x & 15);
+  const int grp = threadIdx.x >> 4;
+  float s[EPU];
+#pragma unroll
+  for (int e = 0; e < EPU; ++e) s[e] = 0.0f;
+  if (u < NU) {
+    for (int b = grp; b < B; b += 16) {
+      const TG *src = gz + ((long)b * NU + u) * EPU;
+      float x[EPU];
+      if constexpr (sizeof(TG) == 2) {
+        bf16x8 v = *reinterpret_cast<const bf16x8 *>(src);
+#pragma unroll
+        for (int e = 0; e < EPU; ++e) x[e] = (float)v[e];
+      } else {
+        f32x4 v = *reinterpret_cast<const f32x4 *>(src);
+#pragma unroll
+        for (int e = 0; e < EPU; ++e) x[e] = v[e];
+      }
+#pragma unroll
+      for (int e = 0; e < EPU; ++e) s[e] += x[e];
+    }
+  }
+  __shared__ float red[16][16][EPU];
+#pragma unroll
+  for (int e = 0; e < EPU; ++e) red[grp][threadIdx.x & 15][e] = s[e];
+  __syncthreads();
+  if (threadIdx.x >= 16 * EPU) return;
+  const int ul = threadIdx.x / EPU, e = threadIdx.x % EPU;
+  const long uu = (long)blockIdx.x * 16 + ul;
+  if (uu >= NU) return;
+  float t = 0.0f;
+  for (int q = 0; q < 16; ++q) t += red[q][ul][e];
+  long c, p;
+  if (vg.blocked) {   // unit = (slice, pixel, part): channels slice*16 + part*EPU + e
+    constexpr int UPP = 16 / EPU;   // units per pixel of a 16-channel slice
+    const long cs = uu / ((long)HW * UPP), rem = uu % ((long)HW * UPP);
+    p = rem / UPP;
+    c = cs * 16 + (rem % UPP) * EPU + e;
+  } else {            // unit = EPU consecutive pixels of one channel
+    c = uu / (HW / EPU);
+    p = (uu % (HW / EPU)) * EPU + e;
+  }
+  db[c * HW + p] = (TD)t;
+}
+
 // ------------------------------------------------------------------ launchers
 template <typename TI, typename TW, typename TO, typename Acc>
 hipError_t conv_fwd_direct(const TI *in, ActView vi, const TW *w, const TW *bias, int bias_pp,
@@ -166,7 +223,13 @@ hipError_t conv_wgrad_direct(const TG *gz, ActView vg, const TI *in, ActView vi,
 }
 template <typename TG, typename Acc, typename TD>
 hipError_t bias_grad(const TG *gz, ActView vg, int B, int per_pixel, TD *db, hipStream_t s) {
-  if (per_pixel) {
+  constexpr int EPU = 16 / (int)sizeof(TG);
+  const long HW = (long)vg.H * vg.W;
+  const bool units = sizeof(Acc) == 4 && (vg.blocked ? (vg.C % 16 == 0) : (HW % EPU == 0));
+  if (per_pixel && units) {
+    const long nu = (long)vg.C * HW / EPU;
+    bias_grad_units_kernel<TG, TD><<<(unsigned)((nu + 15) / 16), 256, 0, s>>>(gz, vg, B, db);
+  } else if (per_pixel) {
     const long n = (long)vg.C * vg.H * vg.W;
     bias_grad_pp_kernel<TG, Acc, TD><<<(unsigned)((n + 255) / 256), 256, 0, s>>>(gz, vg, B, db);
   } else {

@@ -146,13 +146,26 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
 
+  // With prefetched staging the accumulators start from the bias (loaded now, while the
+  // first slice is staged), so the epilogue issues no loads.
+  constexpr bool PREBIAS = ASYNC && EPI == EPI_BIAS;
   f32x16 acc[ROWS][NCT];
 #pragma unroll
-  for (int i = 0; i < ROWS; ++i)
+  for (int i = 0; i < ROWS; ++i) {
+    const int gi = bi0 + wave * ROWS + i, gj = bj0 + px;
+    const bool live = gi < H && gj < W;
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) acc[i][c][r] = 0.0f;
+      for (int q = 0; q < 4; ++q)
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const int co = c * 32 + 8 * q + 4 * h + e;
+          float b0v = 0.0f;
+          if (PREBIAS && live) b0v = bias_pp ? bias[((long)co * H + gi) * W + gj] : bias[co];
+          acc[i][c][4 * q + e] = b0v;
+        }
+  }
 
   // unit k of this thread (u = k NT + tid, [row][chunk][col] order) of slice sl, zero
   // outside the image
@@ -274,7 +287,11 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
         float vals[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) vals[e] = acc[i][c][4 * q + e] * oscale;
-        if constexpr (EPI == EPI_BIAS) {
+        if constexpr (PREBIAS) {
+#pragma unroll
+          for (int e = 0; e < 4; ++e)
+            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+        } else if constexpr (EPI == EPI_BIAS) {
           float bv[4];
           if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
 #pragma unroll
