@@ -195,10 +195,21 @@ DSI_INLINE i32x4 window8(const i32x4 &lo, const i32x4 &hi, int s) {
   }
 }
 
+// Source of the zero units that halo positions outside the image load through the
+// direct-to-LDS loads (those take a global address in every lane).
+__device__ __attribute__((aligned(16))) unsigned int wg_zero_unit[4] = {0u, 0u, 0u, 0u};
+
 // conv2 weight gradient from channel-major g [B][32][H][W] and a [B][CIN][H][W]
-// (W % 8 == 0): the same blocks, strips and MFMA walk as conv_wgrad_mid_kernel, but the
-// strips are staged with 16-byte vector loads and stores (8 columns of one channel);
-// the A strip is shifted by the block's v - 5 through a funnel of two aligned vectors.
+// (W % 8 == 0).  Same blocks and MFMA walk as conv_wgrad_mid_kernel, but a strip
+// covers 64 ACTIVATION columns j' = j0 .. j0+63 and the gradient is the shifted
+// operand: dW[co][ci][u][v] = sum_{i,j'} G[co][i][j' - v + 5] A[ci][i + u - 5][j'],
+// which counts every (i, j) once over the strips.  The activation strip is aligned, so
+// it streams into LDS with direct-to-LDS loads (global_load_lds_dwordx4) issued right
+// after the walk's fragments have been read into registers: they land while the walk's
+// MFMAs run, and no LDS read follows them until the next strip (the compiler makes
+// every LDS read wait for such loads).  The gradient strip (8 rows, shifted by
+// 5 - v) goes through registers (two aligned vectors and a funnel shift per unit),
+// loaded at the same time and stored after the walk.
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *__restrict__ g,
                                                                     const bf16 *__restrict__ a,
@@ -208,12 +219,13 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *
   // multiple of 256: the 32 lanes of a half-wave read 32 channels of the same (row,
   // col), which then fall on distinct banks
   constexpr int GS = WG_SR * WG_TW + 8, AS = WG_LR * WG_TW + 8;   // channel strides (elements)
+  constexpr int AU = WG_LR * 8;                                    // 16-byte units per A channel
   __shared__ __attribute__((aligned(16))) bf16 gl[32 * GS];
   __shared__ __attribute__((aligned(16))) bf16 al[32 * AS];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
   const int chunk = blockIdx.x % nchunk, v = (blockIdx.x / nchunk) % 11, ct = blockIdx.x / nchunk / 11;
   const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
-  const int sh = (v + 3) & 7;   // (v - 5) mod 8: offset of the A window in its aligned vectors
+  const int sg = (13 - v) & 7;   // (5 - v) mod 8: offset of the G window in its aligned vectors
 
   f32x16 acc[11];
 #pragma unroll
@@ -221,74 +233,92 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[u][r] = 0.0f;
 
-  // one A unit (channel c, row, 8-column group k): the window of two aligned vectors
-  auto a_load = [&](int b, int i0, int j0, int idx, i32x4 &lo, i32x4 &hi) {
-    const int c = idx / (WG_LR * 8), rem = idx - c * (WG_LR * 8), row = rem >> 3, k = rem & 7;
-    const int gi = i0 - 5 + row, base = j0 + v - 5 + 8 * k - sh;   // aligned
+  // strips in order (image, row strip, column strip)
+  const int nsi = (H + WG_SR - 1) / WG_SR, nsj = (W + WG_TW - 1) / WG_TW;
+  const int nstrip = (b1 - b0) * nsi * nsj;
+  auto strip_at = [&](int q, int &b, int &i0, int &j0) {
+    b = b0 + q / (nsi * nsj);
+    const int r = q % (nsi * nsj);
+    i0 = (r / nsj) * WG_SR;
+    j0 = (r % nsj) * WG_TW;
+  };
+  // A strip: wave w issues DMA instruction d = w + 4 t (t < 24) = (channel d / 3, part d % 3);
+  // part 2 has 16 units (lanes 16..63 idle)
+  auto a_dma = [&](int b, int i0, int j0) {
+#pragma unroll
+    for (int t = 0; t < 24; ++t) {
+      const int d = wave + 4 * t, c = d / 3, part = d % 3;
+      const int u = part * 64 + lane;
+      if (u < AU) {
+        const int row = u >> 3, k = u & 7;
+        const int gi = i0 - 5 + row, gj = j0 + 8 * k;
+        const void *src = reinterpret_cast<const void *>(wg_zero_unit);
+        if (gi >= 0 && gi < H && gj < W) src = a + (((long)b * CIN + ct * 32 + c) * H + gi) * W + gj;
+        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(al + c * AS + part * 64 * 8),
+                                         16, 0, 0);
+      }
+    }
+  };
+  // G strip unit idx (channel c, row, 8-column group k) from two aligned vectors
+  auto g_load = [&](int b, int i0, int j0, int idx, i32x4 &lo, i32x4 &hi) {
+    const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
+    const int gi = i0 + row, base = j0 - v + 5 + 8 * k - sg;   // aligned
     lo = hi = i32x4{0, 0, 0, 0};
-    if (gi >= 0 && gi < H) {
-      const bf16 *src = a + (((long)b * CIN + ct * 32 + c) * H + gi) * W;
+    if (gi < H) {
+      const bf16 *src = g + (((long)b * 32 + c) * H + gi) * W;
       if (base >= 0 && base < W) lo = *reinterpret_cast<const i32x4 *>(src + base);
       if (base + 8 >= 0 && base + 8 < W) hi = *reinterpret_cast<const i32x4 *>(src + base + 8);
     }
   };
-  auto a_store = [&](int idx, const i32x4 &lo, const i32x4 &hi) {
-    const int c = idx / (WG_LR * 8), rem = idx - c * (WG_LR * 8), row = rem >> 3, k = rem & 7;
-    *reinterpret_cast<i32x4 *>(al + c * AS + row * WG_TW + 8 * k) = window8(lo, hi, sh);
+  constexpr int IG = 32 * WG_SR * 8 / 256;   // G units per thread
+  auto g_store = [&](int idx, const i32x4 &lo, const i32x4 &hi) {
+    const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
+    *reinterpret_cast<i32x4 *>(gl + c * GS + row * WG_TW + 8 * k) = window8(lo, hi, sg);
   };
 
-  for (int b = b0; b < b1; ++b)
-    for (int i0 = 0; i0 < H; i0 += WG_SR)
-      for (int j0 = 0; j0 < W; j0 += WG_TW) {
-        __syncthreads();
-        // two round trips per strip: G and the first half of A, then the rest of A
-        constexpr int IG = 32 * WG_SR * 8 / 256, IA = 32 * WG_LR * 8 / 256, IA1 = IA / 2;
-        static_assert(32 * WG_LR * 8 % 256 == 0 && IA % 2 == 0, "A units split evenly");
-        {
-          i32x4 gv[IG], lo[IA1], hi[IA1];
+  if (nstrip > 0) {
+    int b, i0, j0;
+    strip_at(0, b, i0, j0);
+    a_dma(b, i0, j0);
+    i32x4 lo[IG], hi[IG];
 #pragma unroll
-          for (int it = 0; it < IG; ++it) {
-            const int idx = tid + it * 256;
-            const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
-            const int gi = i0 + row, gj = j0 + 8 * k;
-            gv[it] = i32x4{0, 0, 0, 0};
-            if (gi < H && gj < W) gv[it] = *reinterpret_cast<const i32x4 *>(g + (((long)b * 32 + c) * H + gi) * W + gj);
-          }
+    for (int it = 0; it < IG; ++it) g_load(b, i0, j0, tid + it * 256, lo[it], hi[it]);
 #pragma unroll
-          for (int j = 0; j < IA1; ++j) a_load(b, i0, j0, tid + j * 256, lo[j], hi[j]);
+    for (int it = 0; it < IG; ++it) g_store(tid + it * 256, lo[it], hi[it]);
+  }
+  for (int q = 0; q < nstrip; ++q) {
+    __builtin_amdgcn_s_waitcnt(0);   // this strip's direct-to-LDS loads have landed
+    __syncthreads();
+    // every fragment of the walk into registers
+    Frag8<bf16> gf[WG_SR], af[WG_LR];
 #pragma unroll
-          for (int it = 0; it < IG; ++it) {
-            const int idx = tid + it * 256;
-            const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
-            *reinterpret_cast<i32x4 *>(gl + c * GS + row * WG_TW + 8 * k) = gv[it];
-          }
+    for (int i = 0; i < WG_SR; ++i)
+      gf[i].v = *reinterpret_cast<const bf16x8 *>(gl + c32 * GS + i * WG_TW + 16 * wave + 8 * h);
 #pragma unroll
-          for (int j = 0; j < IA1; ++j) a_store(tid + j * 256, lo[j], hi[j]);
-        }
-        {
-          i32x4 lo[IA - IA1], hi[IA - IA1];
+    for (int r = 0; r < WG_LR; ++r)
+      af[r].v = *reinterpret_cast<const bf16x8 *>(al + c32 * AS + r * WG_TW + 16 * wave + 8 * h);
+    __syncthreads();                 // the LDS tiles are free
+    const bool more = q + 1 < nstrip;
+    i32x4 lo[IG], hi[IG];
+    if (more) {
+      int b, i0, j0;
+      strip_at(q + 1, b, i0, j0);
+      a_dma(b, i0, j0);
 #pragma unroll
-          for (int j = 0; j < IA - IA1; ++j) a_load(b, i0, j0, tid + (IA1 + j) * 256, lo[j], hi[j]);
+      for (int it = 0; it < IG; ++it) g_load(b, i0, j0, tid + it * 256, lo[it], hi[it]);
+    }
 #pragma unroll
-          for (int j = 0; j < IA - IA1; ++j) a_store(tid + (IA1 + j) * 256, lo[j], hi[j]);
-        }
-        __syncthreads();
-        Frag8<bf16> gf[WG_SR];
+    for (int r = 0; r < WG_LR; ++r)
 #pragma unroll
-        for (int i = 0; i < WG_SR; ++i)
-          gf[i].v = *reinterpret_cast<const bf16x8 *>(gl + c32 * GS + i * WG_TW + 16 * wave + 8 * h);
-        const bf16 *arow = al + c32 * AS + 16 * wave + 8 * h;
-#pragma unroll
-        for (int r = 0; r < WG_LR; ++r) {
-          Frag8<bf16> af;
-          af.v = *reinterpret_cast<const bf16x8 *>(arow + r * WG_TW);
-#pragma unroll
-          for (int u = 0; u < 11; ++u) {
-            const int i = r - u;
-            if (i >= 0 && i < WG_SR) gf[i].mma(af, acc[u]);
-          }
-        }
+      for (int u = 0; u < 11; ++u) {
+        const int i = r - u;
+        if (i >= 0 && i < WG_SR) gf[i].mma(af[r], acc[u]);
       }
+    if (more) {
+#pragma unroll
+      for (int it = 0; it < IG; ++it) g_store(tid + it * 256, lo[it], hi[it]);
+    }
+  }
   float *dst = partial + ((long)blockIdx.x * 4 + wave) * 11 * 64 * 16;
 #pragma unroll
   for (int u = 0; u < 11; ++u)
