@@ -59,6 +59,16 @@ DSI_INLINE float e4m3_to_f32(u8 c) {
   return s ? -v : v;
 }
 
+// ------------------------------------------------------------------ XCDs
+// The workgroups of a launch go to the 8 XCDs in turn (block i to XCD i % 8), and each
+// XCD has its own L2.  xcd_logical(i, n) renumbers the n blocks of a grid so that
+// every XCD runs one contiguous range of logical indices: blocks that read the same
+// data, given neighbouring logical indices, then run side by side on one L2.
+DSI_INLINE int xcd_logical(int i, int n) {
+  const int x = i & 7, q = n >> 3, r = n & 7;
+  return x * q + (x < r ? x : r) + (i >> 3);
+}
+
 // ------------------------------------------------------------------ MFMA
 // 32x32 result tile, lane l holds D[8*(r/4) + 4*(l/32) + r%4][l%32] in acc[r].
 DSI_INLINE int mfma_row(int lane, int r) { return 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3); }

@@ -13,8 +13,9 @@
 // the block stages its A strip already shifted by its tap column, so the read is
 // a 16-byte aligned LDS load) feeding up to 8 MFMAs (one per u).
 // Accumulators (11 u x 32 x 32) live across all strips and images of the
-// block; each block then writes its raw accumulators, and a second kernel sums
-// the partials in a fixed order (deterministic).
+// block; each block then sums its four waves' accumulators in wave order and
+// writes them, and a second kernel sums the blocks' partials in a fixed order
+// (deterministic).
 #include "common.h"
 #include "internal.h"
 
@@ -26,8 +27,37 @@ constexpr int WG_TW = 64;           // output columns per pass (4 waves x 16)
 constexpr int WG_GW = WG_TW + 8;    // G tile row pitch (elements)
 constexpr int WG_AW = WG_TW + 16;   // A tile row pitch (64 columns + padding)
 
+// Sums the four waves' accumulators in wave order through LDS and stores the block's
+// partial: per filter row u, the 1024 sums of the 32 x 32 tile as [r/4][lane][r%4]
+// (THIN: only the 11 used band columns, 352 sums as [r/4][lane/32][lane%32 < 11][r%4]).
+// red: 8192 floats of LDS that no wave still reads (the caller synchronises first).
+template <bool THIN>
+DSI_INLINE void store_block_partial(const f32x16 (&acc)[11], float *red, float *__restrict__ dst) {
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  constexpr int NQ = THIN ? 88 : 256;   // 4-float groups per u
+  const int src = THIN ? (tid / 22) * 64 + ((tid / 11) & 1) * 32 + tid % 11 : tid;
+#pragma unroll
+  for (int u = 0; u < 11; ++u) {
+    float *buf = red + (u & 1) * 4096;   // two buffers: one barrier per u
+#pragma unroll
+    for (int r4 = 0; r4 < 4; ++r4)
+      *reinterpret_cast<f32x4 *>(buf + ((wave * 4 + r4) * 64 + lane) * 4) =
+          f32x4{acc[u][4 * r4], acc[u][4 * r4 + 1], acc[u][4 * r4 + 2], acc[u][4 * r4 + 3]};
+    __syncthreads();
+    if (tid < NQ) {
+      f32x4 t = *reinterpret_cast<const f32x4 *>(buf + src * 4);
+#pragma unroll
+      for (int w = 1; w < 4; ++w) {
+        const f32x4 x = *reinterpret_cast<const f32x4 *>(buf + (w * 256 + src) * 4);
+        t = f32x4{t[0] + x[0], t[1] + x[1], t[2] + x[2], t[3] + x[3]};
+      }
+      *reinterpret_cast<f32x4 *>(dst + (u * NQ + tid) * 4) = t;
+    }
+  }
+}
+
 // g [B][2][H][W][16] (T), a [B][CIN/16][H][W][16] (T)
-// partial [(ct*11 + v)*nchunk + chunk][4 waves][11 u][64 lanes][16] fp32
+// partial [(ct*11 + v)*nchunk + chunk][11 u][1024] fp32 (store_block_partial)
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restrict__ g, const bf16 *__restrict__ a,
                                                              float *__restrict__ partial, int B, int H, int W,
@@ -35,7 +65,9 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restr
   __shared__ __attribute__((aligned(16))) bf16 gl[32 * WG_SR * WG_GW];
   __shared__ __attribute__((aligned(16))) bf16 al[32 * WG_LR * WG_AW];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
-  const int chunk = blockIdx.x % nchunk, v = (blockIdx.x / nchunk) % 11, ct = blockIdx.x / nchunk / 11;
+  // the (CIN/32) * 11 blocks of one image chunk read the same data: neighbours on one XCD
+  const int L = xcd_logical(blockIdx.x, gridDim.x), ncombo = (CIN / 32) * 11;
+  const int chunk = L / ncombo, v = (L % ncombo) % 11, ct = (L % ncombo) / 11;
   const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
 
   f32x16 acc[11];
@@ -125,12 +157,9 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_kernel(const bf16 *__restr
           }
         }
       }
-  float *dst = partial + ((long)blockIdx.x * 4 + wave) * 11 * 64 * 16;
-#pragma unroll
-  for (int u = 0; u < 11; ++u)
-#pragma unroll
-    for (int r = 0; r < 16; r += 4)
-      *reinterpret_cast<f32x4 *>(dst + (u * 64 + lane) * 16 + r) = f32x4{acc[u][r], acc[u][r + 1], acc[u][r + 2], acc[u][r + 3]};
+  __syncthreads();
+  store_block_partial<false>(acc, reinterpret_cast<float *>(al),
+                             partial + ((long)(ct * 11 + v) * nchunk + chunk) * 11 * 1024);
 }
 
 // ------------------------------------------------------------------------
@@ -200,16 +229,19 @@ DSI_INLINE i32x4 window8(const i32x4 &lo, const i32x4 &hi, int s) {
 __device__ __attribute__((aligned(16))) unsigned int wg_zero_unit[4] = {0u, 0u, 0u, 0u};
 
 // conv2 weight gradient from channel-major g [B][32][H][W] and a [B][CIN][H][W]
-// (W % 8 == 0).  Same blocks and MFMA walk as conv_wgrad_mid_kernel, but a strip
-// covers 64 ACTIVATION columns j' = j0 .. j0+63 and the gradient is the shifted
-// operand: dW[co][ci][u][v] = sum_{i,j'} G[co][i][j' - v + 5] A[ci][i + u - 5][j'],
-// which counts every (i, j) once over the strips.  The activation strip is aligned, so
-// it streams into LDS with direct-to-LDS loads (global_load_lds_dwordx4) issued right
-// after the walk's fragments have been read into registers: they land while the walk's
-// MFMAs run, and no LDS read follows them until the next strip (the compiler makes
-// every LDS read wait for such loads).  The gradient strip (8 rows, shifted by
-// 5 - v) goes through registers (two aligned vectors and a funnel shift per unit),
-// loaded at the same time and stored after the walk.
+// (W % 8 == 0, CIN * H * W < 2^31).  Same blocks and MFMA walk as
+// conv_wgrad_mid_kernel, but a strip covers 64 ACTIVATION columns j' = j0 .. j0+63 and
+// the gradient is the shifted operand:
+//   dW[co][ci][u][v] = sum_{i,j'} G[co][i][j' - v + 5] A[ci][i + u - 5][j'],
+// which counts every (i, j) once over the strips.  Per strip a wave first reads every
+// fragment of its walk into registers; then, while its MFMAs run, it issues the next
+// strip's loads between them: the activation strip (aligned) with direct-to-LDS loads
+// (global_load_lds_dwordx4), the gradient strip (8 rows, shifted by 5 - v) into
+// registers as two aligned vectors per unit, funnel-shifted and stored after the walk.
+// No LDS read follows the direct-to-LDS loads until the next strip (the compiler makes
+// every LDS read wait for them).  Positions outside the image load a zero unit, so no
+// load sits behind a branch, and the last strip re-loads itself (harmless) for the same
+// reason.
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *__restrict__ g,
                                                                     const bf16 *__restrict__ a,
@@ -219,13 +251,17 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *
   // multiple of 256: the 32 lanes of a half-wave read 32 channels of the same (row,
   // col), which then fall on distinct banks
   constexpr int GS = WG_SR * WG_TW + 8, AS = WG_LR * WG_TW + 8;   // channel strides (elements)
-  constexpr int AU = WG_LR * 8;                                    // 16-byte units per A channel
   __shared__ __attribute__((aligned(16))) bf16 gl[32 * GS];
   __shared__ __attribute__((aligned(16))) bf16 al[32 * AS];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
-  const int chunk = blockIdx.x % nchunk, v = (blockIdx.x / nchunk) % 11, ct = blockIdx.x / nchunk / 11;
+  const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, c32 = lane & 31;
+  const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
+  // the (CIN/32) * 11 blocks of one image chunk read the same data: neighbours on one XCD
+  const int L = xcd_logical(blockIdx.x, gridDim.x), ncombo = (CIN / 32) * 11;
+  const int chunk = L / ncombo, v = (L % ncombo) % 11, ct = (L % ncombo) / 11;
   const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
   const int sg = (13 - v) & 7;   // (5 - v) mod 8: offset of the G window in its aligned vectors
+  const bf16 *zero = reinterpret_cast<const bf16 *>(wg_zero_unit);
+  const int urow = lane >> 3, ucol = 8 * (lane & 7);   // a lane's unit in an 8-row x 64-column part
 
   f32x16 acc[11];
 #pragma unroll
@@ -233,58 +269,55 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[u][r] = 0.0f;
 
-  // strips in order (image, row strip, column strip)
-  const int nsi = (H + WG_SR - 1) / WG_SR, nsj = (W + WG_TW - 1) / WG_TW;
-  const int nstrip = (b1 - b0) * nsi * nsj;
-  auto strip_at = [&](int q, int &b, int &i0, int &j0) {
-    b = b0 + q / (nsi * nsj);
-    const int r = q % (nsi * nsj);
-    i0 = (r / nsj) * WG_SR;
-    j0 = (r % nsj) * WG_TW;
+  // A strip rows i0-5 .. i0+12 of channel c as three parts of 8 rows (the third: 2 rows,
+  // lanes 0..15); wave w issues the 24 (channel, part) loads of channels 8w .. 8w+7
+  auto a_dma = [&](int t, const bf16 *aimg, int i0, int j0) {
+    const int c = 8 * wave + t / 3, part = t % 3;
+    if (part == 2 && lane >= 16) return;
+    const int gi = i0 - 5 + 8 * part + urow, gj = j0 + ucol;
+    const bool in = gi >= 0 && gi < H && gj < W;
+    const bf16 *src = in ? aimg + (c * H + gi) * W + gj : zero;
+    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(al + c * AS + part * 64 * 8), 16,
+                                     0, 0);
   };
-  // A strip: wave w issues DMA instruction d = w + 4 t (t < 24) = (channel d / 3, part d % 3);
-  // part 2 has 16 units (lanes 16..63 idle)
-  auto a_dma = [&](int b, int i0, int j0) {
-#pragma unroll
-    for (int t = 0; t < 24; ++t) {
-      const int d = wave + 4 * t, c = d / 3, part = d % 3;
-      const int u = part * 64 + lane;
-      if (u < AU) {
-        const int row = u >> 3, k = u & 7;
-        const int gi = i0 - 5 + row, gj = j0 + 8 * k;
-        const void *src = reinterpret_cast<const void *>(wg_zero_unit);
-        if (gi >= 0 && gi < H && gj < W) src = a + (((long)b * CIN + ct * 32 + c) * H + gi) * W + gj;
-        __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(al + c * AS + part * 64 * 8),
-                                         16, 0, 0);
+  // G strip unit (channel wave + 4 it, row urow, column group) from two aligned vectors
+  auto g_load = [&](int it, const bf16 *gimg, int i0, int j0, i32x4 &lo, i32x4 &hi) {
+    const int c = wave + 4 * it, gi = i0 + urow, base = j0 - v + 5 + ucol - sg;   // aligned
+    const bf16 *row = gimg + (c * H + gi) * W;
+    const bool rin = gi < H;
+    lo = *reinterpret_cast<const i32x4 *>(rin && base >= 0 && base < W ? row + base : zero);
+    hi = *reinterpret_cast<const i32x4 *>(rin && base + 8 >= 0 && base + 8 < W ? row + base + 8 : zero);
+  };
+  constexpr int IG = 32 * WG_SR * 8 / 256;   // G units per thread
+  auto g_store = [&](int it, const i32x4 &lo, const i32x4 &hi) {
+    const int c = wave + 4 * it;
+    *reinterpret_cast<i32x4 *>(gl + c * GS + urow * WG_TW + ucol) = window8(lo, hi, sg);
+  };
+
+  // strips in order (image, row strip, column strip); (nb, ni, nj) is the next one staged
+  const int nstrip = (b1 - b0) * ((H + WG_SR - 1) / WG_SR) * ((W + WG_TW - 1) / WG_TW);
+  int nb = b0, ni = 0, nj = 0;
+  auto advance = [&]() {
+    nj += WG_TW;
+    if (nj >= W) {
+      nj = 0;
+      ni += WG_SR;
+      if (ni >= H) {
+        ni = 0;
+        ++nb;
       }
     }
   };
-  // G strip unit idx (channel c, row, 8-column group k) from two aligned vectors
-  auto g_load = [&](int b, int i0, int j0, int idx, i32x4 &lo, i32x4 &hi) {
-    const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
-    const int gi = i0 + row, base = j0 - v + 5 + 8 * k - sg;   // aligned
-    lo = hi = i32x4{0, 0, 0, 0};
-    if (gi < H) {
-      const bf16 *src = g + (((long)b * 32 + c) * H + gi) * W;
-      if (base >= 0 && base < W) lo = *reinterpret_cast<const i32x4 *>(src + base);
-      if (base + 8 >= 0 && base + 8 < W) hi = *reinterpret_cast<const i32x4 *>(src + base + 8);
-    }
-  };
-  constexpr int IG = 32 * WG_SR * 8 / 256;   // G units per thread
-  auto g_store = [&](int idx, const i32x4 &lo, const i32x4 &hi) {
-    const int c = idx >> 6, row = (idx >> 3) & 7, k = idx & 7;
-    *reinterpret_cast<i32x4 *>(gl + c * GS + row * WG_TW + 8 * k) = window8(lo, hi, sg);
-  };
-
   if (nstrip > 0) {
-    int b, i0, j0;
-    strip_at(0, b, i0, j0);
-    a_dma(b, i0, j0);
+    const bf16 *aimg = a + ((long)nb * CIN + ct * 32) * H * W, *gimg = g + (long)nb * 32 * H * W;
+#pragma unroll
+    for (int t = 0; t < 24; ++t) a_dma(t, aimg, ni, nj);
     i32x4 lo[IG], hi[IG];
 #pragma unroll
-    for (int it = 0; it < IG; ++it) g_load(b, i0, j0, tid + it * 256, lo[it], hi[it]);
+    for (int it = 0; it < IG; ++it) g_load(it, gimg, ni, nj, lo[it], hi[it]);
 #pragma unroll
-    for (int it = 0; it < IG; ++it) g_store(tid + it * 256, lo[it], hi[it]);
+    for (int it = 0; it < IG; ++it) g_store(it, lo[it], hi[it]);
+    advance();
   }
   for (int q = 0; q < nstrip; ++q) {
     __builtin_amdgcn_s_waitcnt(0);   // this strip's direct-to-LDS loads have landed
@@ -298,33 +331,33 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *
     for (int r = 0; r < WG_LR; ++r)
       af[r].v = *reinterpret_cast<const bf16x8 *>(al + c32 * AS + r * WG_TW + 16 * wave + 8 * h);
     __syncthreads();                 // the LDS tiles are free
-    const bool more = q + 1 < nstrip;
+    const int sb = nb < b1 ? nb : b1 - 1;   // after the last strip: a valid strip, loaded again
+    const bf16 *aimg = a + ((long)sb * CIN + ct * 32) * H * W, *gimg = g + (long)sb * 32 * H * W;
     i32x4 lo[IG], hi[IG];
-    if (more) {
-      int b, i0, j0;
-      strip_at(q + 1, b, i0, j0);
-      a_dma(b, i0, j0);
+    // the walk, with the next strip's loads spread between its MFMAs (the gradient's
+    // first, so the stores after the walk wait for them alone)
 #pragma unroll
-      for (int it = 0; it < IG; ++it) g_load(b, i0, j0, tid + it * 256, lo[it], hi[it]);
-    }
-#pragma unroll
-    for (int r = 0; r < WG_LR; ++r)
+    for (int r = 0; r < WG_LR; ++r) {
 #pragma unroll
       for (int u = 0; u < 11; ++u) {
         const int i = r - u;
         if (i >= 0 && i < WG_SR) gf[i].mma(af[r], acc[u]);
       }
-    if (more) {
-#pragma unroll
-      for (int it = 0; it < IG; ++it) g_store(tid + it * 256, lo[it], hi[it]);
+      if (r < IG) g_load(r, gimg, ni, nj, lo[r], hi[r]);
+      if (r >= 2 && r < 14) {
+        a_dma(2 * (r - 2), aimg, ni, nj);
+        a_dma(2 * (r - 2) + 1, aimg, ni, nj);
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
+#pragma unroll
+    for (int it = 0; it < IG; ++it) g_store(it, lo[it], hi[it]);
+    advance();
   }
-  float *dst = partial + ((long)blockIdx.x * 4 + wave) * 11 * 64 * 16;
-#pragma unroll
-  for (int u = 0; u < 11; ++u)
-#pragma unroll
-    for (int r = 0; r < 16; r += 4)
-      *reinterpret_cast<f32x4 *>(dst + (u * 64 + lane) * 16 + r) = f32x4{acc[u][r], acc[u][r + 1], acc[u][r + 2], acc[u][r + 3]};
+  __builtin_amdgcn_s_waitcnt(0);     // the last strip's repeated loads have landed
+  __syncthreads();
+  store_block_partial<false>(acc, reinterpret_cast<float *>(al),
+                             partial + ((long)(ct * 11 + v) * nchunk + chunk) * 11 * 1024);
 }
 
 // Partial-sum reduction: a block owns RED_SLOTS consecutive accumulator slots; its
@@ -342,34 +375,35 @@ DSI_INLINE float reduce_parts(float s) {
   return t;
 }
 
-// dW[co][ci][u][v] = sum over chunks and waves of the partials (fixed order).  Slots
-// (u, lane, r) of one (ci tile, tap column) group are consecutive partials.
+// dW[co][ci][u][v] = sum over chunks of the blocks' partials (fixed order).  Slots
+// (u, q) of one (ci tile, tap column) group are consecutive partials, q = the
+// [r/4][lane][r%4] position in the 32 x 32 tile.
 __global__ __launch_bounds__(256) void conv_wgrad_mid_reduce_kernel(const float *__restrict__ partial,
                                                                     float *__restrict__ dw, int CIN, int nchunk) {
   const long idx = (long)blockIdx.x * RED_SLOTS + (threadIdx.x % RED_SLOTS);
   const int part = threadIdx.x / RED_SLOTS;
-  const long nslot = (long)(CIN / 32) * 11 * 11 * 64 * 16;
-  const int slot = (int)(idx % (11 * 64 * 16));       // (u, lane, r)
-  const int grp = (int)(idx / (11 * 64 * 16));        // ct * 11 + v
+  const long nslot = (long)(CIN / 32) * 11 * 11 * 1024;
+  const int slot = (int)(idx % (11 * 1024));   // (u, q)
+  const int grp = (int)(idx / (11 * 1024));    // ct * 11 + v
   float s = 0.0f;
   if (idx < nslot) {
-    const float *p = partial + (long)grp * nchunk * 4 * 11 * 64 * 16 + slot;
-    for (int cw = part; cw < nchunk * 4; cw += RED_PARTS) s += p[(long)cw * 11 * 64 * 16];
+    const float *p = partial + (long)grp * nchunk * 11 * 1024 + slot;
+    for (int c = part; c < nchunk; c += RED_PARTS) s += p[(long)c * 11 * 1024];
   }
   s = reduce_parts(s);
   if (part != 0 || idx >= nslot) return;
-  const int u = slot / 1024, lane = (slot / 16) & 63, r = slot & 15;
+  const int u = slot / 1024, q = slot % 1024, lane = (q >> 2) & 63, r = (q >> 8) * 4 + (q & 3);
   const int v = grp % 11, ct = grp / 11;
-  const int co = 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3), ci = ct * 32 + (lane & 31);
+  const int co = mfma_row(lane, r), ci = ct * 32 + (lane & 31);
   dw[(((long)co * CIN + ci) * 11 + u) * 11 + v] = s;
 }
 
-size_t conv_wgrad_mid_partial_floats(int CIN, int nchunk) { return (size_t)(CIN / 32) * 11 * nchunk * 4 * 11 * 64 * 16; }
+size_t conv_wgrad_mid_partial_floats(int CIN, int nchunk) { return (size_t)(CIN / 32) * 11 * nchunk * 11 * 1024; }
 
 hipError_t conv_wgrad_mid(const bf16 *g, const bf16 *a, int CIN, float *partial, int nchunk, float *dw, int B,
                           int H, int W, hipStream_t s, bool planar) {
   const int blocks = (CIN / 32) * 11 * nchunk;
-  if (planar && W % 8 != 0) return hipErrorInvalidValue;
+  if (planar && (W % 8 != 0 || (long)CIN * H * W >= (1L << 31))) return hipErrorInvalidValue;
   if (CIN == 64 && planar)
     conv_wgrad_mid_planar_kernel<64><<<blocks, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
   else if (CIN == 64)
@@ -380,7 +414,7 @@ hipError_t conv_wgrad_mid(const bf16 *g, const bf16 *a, int CIN, float *partial,
     return hipErrorInvalidValue;
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const long n = (long)(CIN / 32) * 11 * 11 * 64 * 16;
+  const long n = (long)(CIN / 32) * 11 * 11 * 1024;
   conv_wgrad_mid_reduce_kernel<<<(unsigned)((n + RED_SLOTS - 1) / RED_SLOTS), RED_SLOTS * RED_PARTS, 0, s>>>(
       partial, dw, CIN, nchunk);
   return hipGetLastError();
@@ -403,7 +437,7 @@ namespace dsi {
 constexpr int TG_PITCH = WG_TW + 16;  // thin tile pitch: cols -5 .. 74 (+ padding)
 
 // wide [B][CW/16][H][W][16] (bf16); thin [B][H][W] (TT, converted to bf16)
-// partial [ct*nchunk + chunk][4 waves][11 u][64 lanes][16] fp32
+// partial [ct*nchunk + chunk][11 u][352] fp32 (store_block_partial)
 template <int MODE, typename TT>
 __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__restrict__ wide, const TT *__restrict__ thin,
                                                               int CW, float *__restrict__ partial, int B, int H, int W,
@@ -533,37 +567,33 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
           }
         }
       }
-  float *dst = partial + ((long)blockIdx.x * 4 + wave) * 11 * 64 * 16;
-#pragma unroll
-  for (int u = 0; u < 11; ++u)
-#pragma unroll
-    for (int r = 0; r < 16; r += 4)
-      *reinterpret_cast<f32x4 *>(dst + (u * 64 + lane) * 16 + r) = f32x4{acc[u][r], acc[u][r + 1], acc[u][r + 2], acc[u][r + 3]};
+  __syncthreads();
+  store_block_partial<true>(acc, reinterpret_cast<float *>(wl), partial + (long)blockIdx.x * 11 * 352);
 }
 
 // dW[m][u][v] (m = the wide channel; layer 3: [1][CW][11][11], layer 1: [CW][1][11][11]:
-// the same linear order) = sum over chunks and waves of the partials (fixed order); a
-// thread owns one accumulator slot (u, lane, r) of one channel tile.
+// the same linear order) = sum over chunks of the blocks' partials (fixed order); a
+// slot is (u, q) of one channel tile, q = the [r/4][lane/32][v][r%4] position.
 __global__ __launch_bounds__(256) void conv_wgrad_thin_reduce_kernel(const float *__restrict__ partial,
                                                                      float *__restrict__ dw, int CW, int nchunk) {
   const int idx = blockIdx.x * RED_SLOTS + (threadIdx.x % RED_SLOTS);
   const int part = threadIdx.x / RED_SLOTS;
-  const int nslot = (CW / 32) * 11 * 64 * 16;
-  const int slot = idx % (11 * 64 * 16), ct = idx / (11 * 64 * 16);
-  const int u = slot / 1024, lane = (slot / 16) & 63, r = slot & 15;
-  const int v = lane & 31;   // tap columns 11..31 of the band are padding
+  const int nslot = (CW / 32) * 11 * 352;
+  const int slot = idx % (11 * 352), ct = idx / (11 * 352);
   float s = 0.0f;
-  if (idx < nslot && v < 11) {
-    const float *p = partial + (long)ct * nchunk * 4 * 11 * 64 * 16 + slot;
-    for (int cw = part; cw < nchunk * 4; cw += RED_PARTS) s += p[(long)cw * 11 * 64 * 16];
+  if (idx < nslot) {
+    const float *p = partial + (long)ct * nchunk * 11 * 352 + slot;
+    for (int c = part; c < nchunk; c += RED_PARTS) s += p[(long)c * 11 * 352];
   }
   s = reduce_parts(s);
-  if (part != 0 || idx >= nslot || v >= 11) return;
-  const int m = ct * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+  if (part != 0 || idx >= nslot) return;
+  const int u = slot / 352, t = (slot % 352) >> 2, e = slot & 3;
+  const int r4 = t / 22, h = (t / 11) & 1, v = t % 11;
+  const int m = ct * 32 + 8 * r4 + 4 * h + e;   // mfma_row(32 h + v, 4 r4 + e)
   dw[((long)m * 11 + u) * 11 + v] = s;
 }
 
-size_t conv_wgrad_thin_partial_floats(int CW, int nchunk) { return (size_t)(CW / 32) * nchunk * 4 * 11 * 64 * 16; }
+size_t conv_wgrad_thin_partial_floats(int CW, int nchunk) { return (size_t)(CW / 32) * nchunk * 11 * 352; }
 
 template <typename TT>
 hipError_t conv_wgrad_thin(int mode, const bf16 *wide, const TT *thin, int CW, float *partial, int nchunk, float *dw,
@@ -575,7 +605,7 @@ hipError_t conv_wgrad_thin(int mode, const bf16 *wide, const TT *thin, int CW, f
     conv_wgrad_thin_kernel<THIN_IN, TT><<<blocks, 256, 0, s>>>(wide, thin, CW, partial, B, H, W, nchunk);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  conv_wgrad_thin_reduce_kernel<<<((CW / 32) * 11 * 64 * 16 + RED_SLOTS - 1) / RED_SLOTS, RED_SLOTS * RED_PARTS, 0,
+  conv_wgrad_thin_reduce_kernel<<<((CW / 32) * 11 * 352 + RED_SLOTS - 1) / RED_SLOTS, RED_SLOTS * RED_PARTS, 0,
                                   s>>>(partial, dw, CW, nchunk);
   return hipGetLastError();
 }

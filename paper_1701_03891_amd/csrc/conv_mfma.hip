@@ -220,6 +220,17 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
     unsigned char *nbuf = lds + ((cs + 1) & 1) * BUF;  // next slice's buffer (ASYNC), unread now
     i32x4 pa0 = {0, 0, 0, 0}, pa1 = {0, 0, 0, 0};     // units loaded one column ago
     int pk = -1;                                       // their first unit index
+    const unsigned char *lrow0 = buf + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + px * 16;
+    // The slice is one walk over (tap column v, input row rr) steps.  With prefetched
+    // staging each step's LDS fragment is read LA steps ahead (across column ends), and a
+    // scheduling barrier after every step keeps the reads there, so a read's latency is
+    // covered by the MFMAs of the steps between (at the band's ends a step has only 1-7).
+    constexpr int NR = ROWS + 2 * RAD, NS = KT * NR, LA = ASYNC ? 6 : 1;
+    Frag8<T> xq[LA];
+    if constexpr (ASYNC) {
+#pragma unroll
+      for (int q = 0; q < LA; ++q) xq[q] = lds_frag<T>(lrow0 + (q / NR) * 16 + (q % NR) * CH16 * PLANE, PLANE);
+    }
     // (unrolled when prefetching: every load then sits in straight-line code, and the
     // waits the compiler places for a column's weights count exactly the later loads)
 #pragma unroll (ASYNC ? KT : 1)
@@ -245,10 +256,17 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
           }
         }
       }
-      const unsigned char *lrow = buf + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + (px + v) * 16;
+      const unsigned char *lrow = lrow0 + v * 16;
 #pragma unroll
-      for (int rr = 0; rr < ROWS + 2 * RAD; ++rr) {
-        Frag8<T> xf = lds_frag<T>(lrow + rr * CH16 * PLANE, PLANE);
+      for (int rr = 0; rr < NR; ++rr) {
+        Frag8<T> xf;
+        if constexpr (ASYNC) {
+          const int st = v * NR + rr, q = st % LA, nx = st + LA;
+          xf = xq[q];
+          if (nx < NS) xq[q] = lds_frag<T>(lrow0 + (nx / NR) * 16 + (nx % NR) * CH16 * PLANE, PLANE);
+        } else {
+          xf = lds_frag<T>(lrow + rr * CH16 * PLANE, PLANE);
+        }
 #pragma unroll
         for (int u = 0; u < KT; ++u) {
           const int i = rr - u;  // output row (within the wave) that input row rr reaches through tap u
@@ -257,6 +275,7 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
             for (int c = 0; c < NCT; ++c) wf[u][c].mma(xf, acc[i][c]);
           }
         }
+        if constexpr (ASYNC) __builtin_amdgcn_sched_barrier(0);
       }
 #pragma unroll
       for (int u = 0; u < KT; ++u)
