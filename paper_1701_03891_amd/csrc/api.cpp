@@ -107,8 +107,6 @@ struct dsi_net {
   // paper path
   void *wp1 = nullptr, *wp2 = nullptr, *wp3 = nullptr;  // packed (compute precision)
   float *bp[3] = {};                                     // fp32 biases (layout of dsi_params)
-  float *w32[3] = {};                                    // OIHW fp32 copies (backward)
-  float *b32[3] = {};                                    // fp32 biases in caller layout (backward)
   void *wp3f = nullptr, *wp2f = nullptr, *wp1f = nullptr;  // packed data-gradient operators
   float w_scale_fc = 1.0f, w_scale_2 = 1.0f;              // FP8 per-tensor weight scales
   unsigned *amax_dev = nullptr;                            // FP8: device scratch for amax
@@ -223,8 +221,6 @@ void free_net_buffers(dsi_net *n) {
   { void *a = n->amax_dev; f(a); n->amax_dev = nullptr; }
   for (int l = 0; l < 3; ++l) {
     void *a = n->bp[l]; f(a); n->bp[l] = nullptr;
-    void *c = n->w32[l]; f(c); n->w32[l] = nullptr;
-    void *e = n->b32[l]; f(e); n->b32[l] = nullptr;
   }
 }
 
@@ -318,8 +314,6 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with
     const int C = d.C[l + 1];
     (void)C;  // per-pixel biases stay planar [C][H][W]: the epilogues read them coalesced
     HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(n->w32[l], p->w[l], wcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
-    HIPCHK(hipMemcpyAsync(n->b32[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
   }
   return DSI_OK;
 }
@@ -481,33 +475,22 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
     if (n->prec == DSI_BF16) return backward_paper<bf16>(n, (const float *)gz_last, sv, L, B, g, gy, scratch, s);
     return backward_paper<float>(n, (const float *)gz_last, sv, L, B, g, gy, scratch, s);
   }
-  // fp32 gradients; activations read in the path's storage (planar fp32, or blocked bf16/fp32)
-  const bool paper = n->path == PATH_PAPER;
+  // generic path: fp32 gradients from planar fp32 activations
   int cmax = 1;
   for (int l = 0; l <= d.L; ++l) cmax = std::max(cmax, d.C[l]);
   float *gbuf[2] = {at<float>(scratch, 0), at<float>(scratch, rnd((size_t)B * cmax * N * 4))};
   const float *gz = (const float *)gz_last;
   for (int l = d.L - 1; l >= 0; --l) {
-    const bool in_blocked = paper && d.C[l] % 16 == 0;
-    ActView vg{d.C[l + 1], H, W, 0}, vi{d.C[l], H, W, in_blocked ? 1 : 0};
-    const void *in = l == 0 ? at<char>(sv, L.xt) : at<char>(sv, L.act[l]);
-    const float *wl = paper ? n->w32[l] : (const float *)n->w[l];
-    if (paper && n->prec == DSI_BF16) {
-      HIPCHK((dsi::conv_wgrad_direct<float, bf16, float, float>(gz, vg, (const bf16 *)in, vi, B, d.k[l], g->w[l], s)));
-    } else {
-      HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>(gz, vg, (const float *)in, vi, B, d.k[l], g->w[l], s)));
-    }
+    ActView vg{d.C[l + 1], H, W, 0}, vi{d.C[l], H, W, 0};
+    const float *in = l == 0 ? at<float>(sv, L.xt) : at<float>(sv, L.act[l]);
+    const float *wl = (const float *)n->w[l];
+    HIPCHK((dsi::conv_wgrad_direct<float, float, float, float>(gz, vg, in, vi, B, d.k[l], g->w[l], s)));
     HIPCHK((dsi::bias_grad<float, float, float>(gz, vg, B, d.bias_per_pixel, g->b[l], s)));
     if (l == 0 && !gy && !(d.fc_trainable && g->w_fc)) break;
     float *go = gbuf[l & 1];
     ActView vo{d.C[l], H, W, 0};
-    if (paper && n->prec == DSI_BF16 && l > 0) {
-      HIPCHK((dsi::conv_dgrad_direct<float, float, bf16, float, float>(gz, vg, wl, (const bf16 *)in, vi, go, vo, B, d.k[l], s)));
-    } else {
-      HIPCHK((dsi::conv_dgrad_direct<float, float, float, float, float>(
-          gz, vg, wl, (l > 0 && !(paper && n->prec == DSI_BF16)) ? (const float *)in : nullptr, vi, go, vo, B,
-          d.k[l], s)));
-    }
+    HIPCHK((dsi::conv_dgrad_direct<float, float, float, float, float>(gz, vg, wl, l > 0 ? in : nullptr, vi, go, vo, B,
+                                                                     d.k[l], s)));
     gz = go;
   }
   if (d.fc_trainable && g->w_fc) HIPCHK(dsi::fc_wgrad_f32(gz, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, s));
@@ -712,11 +695,7 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
     A(&n->wp3f, (size_t)11 * 1 * 64 * 8 * n->es);
     A(&n->wp2f, (size_t)32 * 64 * 121 * n->es);
     A(&n->wp1f, (size_t)64 * 121 * n->es);
-    for (int l = 0; l < 3; ++l) {
-      A((void **)&n->bp[l], bcount(d, l) * 4);
-      A((void **)&n->w32[l], wcount(d, l) * 4);
-      A((void **)&n->b32[l], bcount(d, l) * 4);
-    }
+    for (int l = 0; l < 3; ++l) A((void **)&n->bp[l], bcount(d, l) * 4);
   }
   if (st == DSI_OK) st = pack_params(n, params, (hipStream_t)stream);
   if (st == DSI_OK && hipStreamSynchronize((hipStream_t)stream) != hipSuccess)

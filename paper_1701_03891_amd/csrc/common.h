@@ -11,6 +11,7 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef int i32x8 __attribute__((ext_vector_type(8)));
 typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x2 __attribute__((ext_vector_type(2)));
 typedef unsigned char u8;
 
 #define DSI_INLINE __device__ __forceinline__
@@ -150,21 +151,6 @@ template <typename T> DSI_INLINE Frag8<T> frag_from(const float *x) {
   } else {
     f.lo = f32x4{x[0], x[1], x[2], x[3]};
     f.hi = f32x4{x[4], x[5], x[6], x[7]};
-  }
-  return f;
-}
-
-// keep elements [0, KEEP) of a fragment slice, zero the rest
-template <typename T, int KEEP> DSI_INLINE Frag8<T> frag_keep_first(Frag8<T> f) {
-  if constexpr (sizeof(T) == 2) {
-#pragma unroll
-    for (int e = KEEP; e < 8; ++e) f.v[e] = (bf16)0.0f;
-  } else {
-#pragma unroll
-    for (int e = KEEP; e < 8; ++e) {
-      if (e < 4) f.lo[e] = 0.0f;
-      else f.hi[e - 4] = 0.0f;
-    }
   }
   return f;
 }

@@ -68,6 +68,18 @@ template <> DSI_INLINE void store4<bf16>(bf16 *dst, float a, float b, float c, f
   v[0] = (bf16)a; v[1] = (bf16)b; v[2] = (bf16)c; v[3] = (bf16)d;
   *reinterpret_cast<bf16x4 *>(dst) = v;
 }
+// BF16 store with ReLU after the conversion: on the bit patterns, max(x, 0) as 16-bit
+// integers is ReLU (negative values and -0 have the sign bit set); floor = 0 applies it,
+// floor = -32768 (the smallest 16-bit integer) leaves the values as they are.
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
+typedef short s16x2 __attribute__((ext_vector_type(2)));
+DSI_INLINE void store4_bf16_floor(bf16 *dst, float a, float b, float c, float d, s16x2 floor) {
+  const s16x2 lo = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2{a, b}), bf16x2));
+  const s16x2 hi = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2{c, d}), bf16x2));
+  *reinterpret_cast<i32x2 *>(dst) = i32x2{__builtin_bit_cast(int, __builtin_elementwise_max(lo, floor)),
+                                          __builtin_bit_cast(int, __builtin_elementwise_max(hi, floor))};
+}
 template <typename T> DSI_INLINE void load4f(const T *src, float *o);
 template <> DSI_INLINE void load4f<float>(const float *src, float *o) {
   f32x4 v = *reinterpret_cast<const f32x4 *>(src);
@@ -143,7 +155,9 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   __shared__ __attribute__((aligned(16))) unsigned char lds[(ASYNC ? 2 : 1) * BUF];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
-  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  // tiles of one image (whose halos overlap) on one XCD, side by side in time
+  const int tl = xcd_logical(blockIdx.x, gridDim.x);
+  const int img = tl / tiles_per_img, t = tl % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
 
   // With prefetched staging the accumulators start from the bias (loaded now, while the
@@ -199,7 +213,7 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
     // 16 consecutive threads store 16 consecutive pixels of one chunk plane (no LDS bank
     // conflicts); a wave reads whole pixels, so its global reads stay contiguous
     // (wider types keep fewer loads in flight: their weight fragments need the registers)
-    stage_units<(LH * LW + 15) / 16 * 16 * CH16, NT, sizeof(T) == 2 ? 16 : 2>(lds, tid, [&](int idx, int &loff) -> const void * {
+    stage_units<(LH * LW + 15) / 16 * 16 * CH16, NT, sizeof(T) == 4 ? 2 : 16>(lds, tid, [&](int idx, int &loff) -> const void * {
       const int chunk = (idx >> 4) % CH16, pix = (idx / (16 * CH16)) * 16 + (idx & 15);
       if (pix >= LH * LW) return nullptr;
       const int row = pix / LW, col = pix - row * LW;
@@ -480,30 +494,44 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   }
   __syncthreads();
 
+  // per-lane element offsets of the lane's 4-channel groups within one output image
+  // (the same for the mask); images are img_stride elements apart
+  const long img_stride = (long)(COUT / OSC) * H * W * OSC;
+  const s16x2 floor = relu ? s16x2{0, 0} : s16x2{-32768, -32768};
+  unsigned ooff[NCT][4];
+#pragma unroll
+  for (int c = 0; c < NCT; ++c)
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int co0 = c * 32 + 8 * q + 4 * h;
+      ooff[c][q] = (unsigned)((((long)(co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC);
+    }
+  // odd start column: read the shifted copy one element earlier (4-byte aligned)
+  const int a0 = px + 8 * h + OFF, odd = NCOPY == 2 ? (a0 & 1) : 0;
+  const T *trow0 = tile + odd * COPY + wave * LWA + a0 - odd;
+
   for (int im = 0; im < nimg; ++im) {
-    const int img = img0 + im;
+    const long obase = (long)(img0 + im) * img_stride;   // uniform: the stores take it as a scalar base
+    TO *const oimg = out + obase;
     float mv[NCT][4][4];
     if constexpr (EPI == EPI_MASK) {  // issued before the MFMAs so their latency overlaps
 #pragma unroll
       for (int c = 0; c < NCT; ++c)
 #pragma unroll
-        for (int q = 0; q < 4; ++q) {
-          const int co0 = c * 32 + 8 * q + 4 * h;
-          const long o = ((((long)img * (COUT / OSC) + co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC;
-          if (live) load4f<T>(mask + o, mv[c][q]);
-        }
+        for (int q = 0; q < 4; ++q)
+          if (live) load4f<T>((mask + obase) + ooff[c][q], mv[c][q]);
     }
     f32x16 acc[NCT];
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
       for (int r = 0; r < 16; ++r) acc[c][r] = 0.0f;
-    // odd start column: read the shifted copy one element earlier (4-byte aligned)
-    const int a0 = px + 8 * h + OFF, odd = NCOPY == 2 ? (a0 & 1) : 0;
-    const T *trow = tile + odd * COPY + (im * LH + wave) * LWA + a0 - odd;
     // taps v = 8h + e of filter row u for output pixel px: LDS pixels px + 8h + e.  2-byte
     // types read each fragment as four 32-bit words (a 16-byte LDS read off a 16-byte
-    // boundary stalls), all 11 issued before the MFMAs
+    // boundary stalls), all 11 issued before the MFMAs.  The slots of taps v >= 11 meet
+    // zero weights, and every element read lies inside the staged (finite) tile row, so
+    // they add exact zeros.
+    const T *trow = trow0 + im * LH * LWA;
     uint32_t xw[KT][sizeof(Frag8<T>) / 4];
 #pragma unroll
     for (int u = 0; u < KT; ++u) {
@@ -515,7 +543,6 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
     for (int u = 0; u < KT; ++u) {
       Frag8<T> xf;
       __builtin_memcpy(&xf, xw[u], sizeof(xf));
-      if (h) xf = frag_keep_first<T, 3>(xf);  // taps v >= 11 are padding: keep them finite-free
 #pragma unroll
       for (int c = 0; c < NCT; ++c) {
         if constexpr (WREG) {
@@ -531,16 +558,20 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        const int co0 = c * 32 + 8 * q + 4 * h;
-        const long o = ((((long)img * (COUT / OSC) + co0 / OSC) * H + gi) * W + gj) * OSC + co0 % OSC;
+        TO *dst = oimg + ooff[c][q];
         float vals[4];
 #pragma unroll
         for (int e = 0; e < 4; ++e) vals[e] = acc[c][4 * q + e];
         if constexpr (EPI == EPI_BIAS) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) {
-            vals[e] += bv[c][q][e];
-            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+          for (int e = 0; e < 4; ++e) vals[e] += bv[c][q][e];
+          if constexpr (sizeof(TO) == 2) {
+            store4_bf16_floor(reinterpret_cast<bf16 *>(dst), vals[0], vals[1], vals[2], vals[3], floor);
+            continue;
+          } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e)
+              if (relu) vals[e] = fmaxf(vals[e], 0.0f);
           }
         } else {
 #pragma unroll
@@ -550,7 +581,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
 #pragma unroll
           for (int e = 0; e < 4; ++e) vals[e] *= oscale;
         }
-        store4<TO>(out + o, vals[0], vals[1], vals[2], vals[3]);
+        store4<TO>(dst, vals[0], vals[1], vals[2], vals[3]);
       }
   }
 }
@@ -581,9 +612,23 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   __shared__ __attribute__((aligned(16))) unsigned char lds[LH * 4 * UNIT_PLANE];
   __shared__ __attribute__((aligned(16))) T wl[KT * KT * CIN + 8];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
-  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  // tiles of one image (whose halos overlap) on one XCD, side by side in time
+  const int tl = xcd_logical(blockIdx.x, gridDim.x);
+  const int img = tl / tiles_per_img, t = tl % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  for (int idx = tid; idx < KT * KT * CIN; idx += 256) wl[idx] = wt[idx];
+  {
+    // weights as 16-byte units, every load issued before the stores
+    constexpr int NWU = KT * KT * CIN / EPU, NIT = (NWU + 255) / 256;
+    i32x4 wv[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int idx = tid + 256 * k;
+      wv[k] = idx < NWU ? *reinterpret_cast<const i32x4 *>(wt + idx * EPU) : i32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k)
+      if (tid + 256 * k < NWU) *reinterpret_cast<i32x4 *>(wl + (tid + 256 * k) * EPU) = wv[k];
+  }
   f32x4 acc[4];
 #pragma unroll
   for (int d = 0; d < 4; ++d) acc[d] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -709,9 +754,23 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
   __shared__ __attribute__((aligned(16))) unsigned char lds[LH * ROWB];
   __shared__ __attribute__((aligned(16))) bf16 wl[(KT + 1) * KT * CIN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
-  const int img = blockIdx.x / tiles_per_img, t = blockIdx.x % tiles_per_img;
+  // tiles of one image (whose halos overlap) on one XCD, side by side in time
+  const int tl = xcd_logical(blockIdx.x, gridDim.x);
+  const int img = tl / tiles_per_img, t = tl % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  for (int idx = tid; idx < (KT + 1) * KT * CIN; idx += 256) wl[idx] = idx < KT * KT * CIN ? wt[idx] : (bf16)0.0f;
+  {
+    // weights as 16-byte units, every load issued before the stores (the v = 11 plane zero)
+    constexpr int NWU = (KT + 1) * KT * CIN / 8, NWL = KT * KT * CIN / 8, NIT = (NWU + 255) / 256;
+    i32x4 wv[NIT];
+#pragma unroll
+    for (int k = 0; k < NIT; ++k) {
+      const int idx = tid + 256 * k;
+      wv[k] = idx < NWL ? *reinterpret_cast<const i32x4 *>(wt + idx * 8) : i32x4{0, 0, 0, 0};
+    }
+#pragma unroll
+    for (int k = 0; k < NIT; ++k)
+      if (tid + 256 * k < NWU) *reinterpret_cast<i32x4 *>(wl + (tid + 256 * k) * 8) = wv[k];
+  }
   f32x4 acc[NP];
 #pragma unroll
   for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
@@ -741,17 +800,32 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
       const i32x4 w = *reinterpret_cast<const i32x4 *>(whead + (2 * p * KT + KT - 1 - min(n, KT - 1)) * CIN);
       z[p] = n < KT ? w : i32x4{0, 0, 0, 0};
     }
+    // The pass is one walk of LH x NP (row, tap pair) steps.  Each step's activation
+    // fragment is read LA steps ahead, and a scheduling barrier after every step keeps the
+    // reads there, so the LDS latency hides behind the MFMAs between.
+    constexpr int NST = LH * NP, LA = 4;
+    auto afrag = [&](int st) {
+      Frag8<bf16> a;
+      a.v = *reinterpret_cast<const bf16x8 *>(abase + (st / NP) * ROWB + 2 * (st % NP) * 32);
+      return a;
+    };
+    Frag8<bf16> aq[LA];
+#pragma unroll
+    for (int q = 0; q < LA; ++q) aq[q] = afrag(q);
 #pragma unroll
     for (int r = 0; r < LH; ++r) {
 #pragma unroll
       for (int p = 0; p < NP; ++p) {
+        const int st = r * NP + p;
+        const Frag8<bf16> a = aq[st % LA];
+        if (st + LA < NST) aq[st % LA] = afrag(st + LA);
         i32x4 band;
 #pragma unroll
         for (int q = 0; q < 4; ++q) band[q] = band_shift(z[p][q], KT - 1 - r);
-        Frag8<bf16> a, b;
-        a.v = *reinterpret_cast<const bf16x8 *>(abase + r * ROWB + 2 * p * 32);
+        Frag8<bf16> b;
         __builtin_memcpy(&b, &band, 16);
         acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[p], 0, 0, 0);
+        __builtin_amdgcn_sched_barrier(0);
       }
     }
   }
@@ -790,6 +864,7 @@ template <typename T, int COUT, int EPI, typename TI, typename TO>
 hipError_t conv_first(const TI *in, const T *wp, const float *bias, int bias_pp, int relu, const T *mask,
                       TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
+  if ((long)COUT * H * W >= (1L << 31)) return hipErrorInvalidValue;   // per-image offsets are 32-bit
   int tw, tpi;
   tiles(H, W, 4, 32, tw, tpi);
   // images per block: enough blocks for two per CU, at most FIRST_IMGS
