@@ -303,18 +303,19 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with
     }
     return DSI_OK;
   }
-  HIPCHK(dsi::pack_first(p->w[0], n->wp1, 64, 0, pr, s));
-  HIPCHK(dsi::pack_mid(p->w[1], n->wp2, 64, 32, 0, pr, s));
-  HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, pr, s));
-  // data-gradient operators: layer 3 (32 <- 1), layer 2 (64 <- 32), layer 1 (1 <- 64)
-  HIPCHK(dsi::pack_first(p->w[2], n->wp3f, 32, 1, pr, s));
-  HIPCHK(dsi::pack_mid(p->w[1], n->wp2f, 32, 64, 1, pr, s));
-  HIPCHK(dsi::pack_last(p->w[0], n->wp1f, 64, 1, pr, s));
+  // forward operators, data-gradient operators (layer 3: 32 <- 1, layer 2: 64 <- 32,
+  // layer 1: 1 <- 64) and the biases (per-pixel biases stay planar [C][H][W]: the
+  // epilogues read them coalesced), in one launch
+  dsi::PaperPack pk{};
   for (int l = 0; l < 3; ++l) {
-    const int C = d.C[l + 1];
-    (void)C;  // per-pixel biases stay planar [C][H][W]: the epilogues read them coalesced
-    HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    pk.w[l] = p->w[l];
+    pk.b[l] = p->b[l];
+    pk.bn[l] = (long)bcount(d, l);
+    pk.bp[l] = n->bp[l];
   }
+  pk.wp1 = n->wp1; pk.wp2 = n->wp2; pk.wp3 = n->wp3;
+  pk.wp3f = n->wp3f; pk.wp2f = n->wp2f; pk.wp1f = n->wp1f;
+  HIPCHK(dsi::pack_paper(pk, pr, s));
   return DSI_OK;
 }
 
@@ -1019,13 +1020,15 @@ dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, 
   const long t = opt->step + 1;
   const float c1 = (float)(1.0 - std::pow((double)opt->beta1, (double)t));
   const float c2 = (float)(1.0 - std::pow((double)opt->beta2, (double)t));
+  // every parameter tensor in one launch
+  dsi::AdamMulti am{};
   for (int l = 0; l < d.L; ++l) {
-    HIPCHK(dsi::adam_f32(params->w[l], g.w[l], opt->m_w[l], opt->v_w[l], wcount(d, l), lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
-    HIPCHK(dsi::adam_f32(params->b[l], g.b[l], opt->m_b[l], opt->v_b[l], bcount(d, l), lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
+    am.seg[am.nseg++] = dsi::AdamSeg{params->w[l], g.w[l], opt->m_w[l], opt->v_w[l], (long)wcount(d, l), nullptr};
+    am.seg[am.nseg++] = dsi::AdamSeg{params->b[l], g.b[l], opt->m_b[l], opt->v_b[l], (long)bcount(d, l), nullptr};
   }
   if (d.fc_trainable)
-    HIPCHK(dsi::adam_f32(params->w_fc, g.w_fc, opt->m_fc, opt->v_fc, (long)net->N * d.M, lr, opt->beta1, opt->beta2,
-                         opt->eps, c1, c2, s));
+    am.seg[am.nseg++] = dsi::AdamSeg{params->w_fc, g.w_fc, opt->m_fc, opt->v_fc, (long)net->N * d.M, nullptr};
+  HIPCHK(dsi::adam_multi(am, lr, opt->beta1, opt->beta2, opt->eps, c1, c2, s));
   opt->step = t;
   return pack_params(net, params, s, d.fc_trainable != 0);
 }

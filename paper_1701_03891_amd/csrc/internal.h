@@ -60,6 +60,16 @@ hipError_t pack_fc(const float *w, void *out, int N, int M, int Mpad, int prec, 
 hipError_t pack_mid(const float *w, void *out, int CIN, int COUT, int flip, int prec, hipStream_t s);
 hipError_t pack_first(const float *w, void *out, int COUT, int flip, int prec, hipStream_t s);
 hipError_t pack_last(const float *w, void *out, int CIN, int flip, int prec, hipStream_t s);
+// all packed operands of the paper's network and its bias copies, one launch
+struct PaperPack {
+  const float *w[3];      // OIHW fp32 weights of the three layers
+  const float *b[3];      // fp32 biases (caller layout)
+  long bn[3];             // bias element counts
+  void *wp1, *wp2, *wp3;  // forward operands (T)
+  void *wp3f, *wp2f, *wp1f;  // data-gradient operators (T)
+  float *bp[3];           // the network's bias copies
+};
+hipError_t pack_paper(const PaperPack &pk, int prec, hipStream_t s);
 hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s);
 hipError_t cast_f32_f64(const float *in, double *out, long n, hipStream_t s);
 hipError_t cast_f64_f32(const double *in, float *out, long n, hipStream_t s);
@@ -78,6 +88,19 @@ hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hip
 hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, hipStream_t s);
 hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
+struct AdamSeg {
+  float *th;
+  const float *g;
+  float *m, *v;
+  long n;
+  float *mirror;  // optional second copy of the updated values (nullptr: none)
+};
+struct AdamMulti {
+  AdamSeg seg[2 * 8 + 1];
+  int nseg;
+};
+hipError_t adam_multi(const AdamMulti &a, float lr, float b1, float b2, float eps, float c1, float c2,
+                      hipStream_t s);
 }  // namespace dsi
 
 namespace dsi {

@@ -22,11 +22,7 @@ __global__ void pack_fc_kernel(const float *__restrict__ w, T *__restrict__ out,
 // conv_mid weights: W [COUT][CIN][11][11] -> [CIN/16][11 v][11 u][COUT/32][64][8].
 // flip = 1 packs the data-gradient operator instead: W'[ci][co][u][v] = W[co][ci][10-u][10-v]
 // (so COUT/CIN below are those of the operator being packed).
-template <typename T>
-__global__ void pack_mid_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN, int COUT, int flip) {
-  const long n = (long)CIN * COUT * 121;
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= n) return;
+DSI_INLINE float pack_mid_val(const float *__restrict__ w, long idx, int CIN, int COUT, int flip) {
   const int e = (int)(idx & 7), lane = (int)((idx >> 3) & 63);
   long rest = idx >> 9;
   const int nct = COUT / 32;
@@ -35,37 +31,80 @@ __global__ void pack_mid_kernel(const float *__restrict__ w, T *__restrict__ out
   const int v = (int)(rest % 11); rest /= 11;
   const int cs = (int)rest;
   const int co = ct * 32 + (lane & 31), ci = cs * 16 + (lane >> 5) * 8 + e;
-  float val;
-  if (!flip) val = w[(((long)co * CIN + ci) * 11 + u) * 11 + v];
-  else val = w[(((long)ci * COUT + co) * 11 + (10 - u)) * 11 + (10 - v)];  // original W[ci][co] (its Cout = CIN here)
-  out[idx] = from_f32<T>(val);
+  if (!flip) return w[(((long)co * CIN + ci) * 11 + u) * 11 + v];
+  return w[(((long)ci * COUT + co) * 11 + (10 - u)) * 11 + (10 - v)];  // original W[ci][co] (its Cout = CIN here)
+}
+template <typename T>
+__global__ void pack_mid_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN, int COUT, int flip) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx >= (long)CIN * COUT * 121) return;
+  out[idx] = from_f32<T>(pack_mid_val(w, idx, CIN, COUT, flip));
 }
 
 // conv_first weights: W [COUT][1][11][11] -> [11 u][COUT/32][64][8], taps v = 8*(lane/32) + e.
 // flip = 1 packs the data-gradient operator of a (COUT -> 1) layer instead, whose
 // weights [1][COUT][11][11] have the same linear order: W'[c][0][u][v] = W[0][c][10-u][10-v].
-template <typename T>
-__global__ void pack_first_kernel(const float *__restrict__ w, T *__restrict__ out, int COUT, int flip) {
+DSI_INLINE float pack_first_val(const float *__restrict__ w, int idx, int COUT, int flip) {
   const int nct = COUT / 32;
-  const int idx = blockIdx.x * 256 + threadIdx.x;
-  if (idx >= 11 * nct * 64 * 8) return;
   const int e = idx & 7, lane = (idx >> 3) & 63, ct = (idx >> 9) % nct, u = (idx >> 9) / nct;
   const int co = ct * 32 + (lane & 31), v = 8 * (lane >> 5) + e;
-  float val = 0.0f;
-  if (v < 11) val = flip ? w[((long)co * 11 + (10 - u)) * 11 + (10 - v)] : w[((long)co * 11 + u) * 11 + v];
-  out[idx] = from_f32<T>(val);
+  if (v >= 11) return 0.0f;
+  return flip ? w[((long)co * 11 + (10 - u)) * 11 + (10 - v)] : w[((long)co * 11 + u) * 11 + v];
+}
+template <typename T>
+__global__ void pack_first_kernel(const float *__restrict__ w, T *__restrict__ out, int COUT, int flip) {
+  const int idx = blockIdx.x * 256 + threadIdx.x;
+  if (idx >= 11 * (COUT / 32) * 64 * 8) return;
+  out[idx] = from_f32<T>(pack_first_val(w, idx, COUT, flip));
 }
 
 // conv_last weights: W [1][CIN][11][11] -> [11 v][11 u][CIN].
 // flip = 1 packs the data-gradient operator of a (1 -> CIN) layer instead:
 // W'[0][c][u][v] = W[c][0][10-u][10-v].
+DSI_INLINE float pack_last_val(const float *__restrict__ w, int idx, int CIN, int flip) {
+  const int c = idx % CIN, u = (idx / CIN) % 11, v = idx / CIN / 11;
+  return flip ? w[((long)c * 11 + (10 - u)) * 11 + (10 - v)] : w[((long)c * 11 + u) * 11 + v];
+}
 template <typename T>
 __global__ void pack_last_kernel(const float *__restrict__ w, T *__restrict__ out, int CIN, int flip) {
   const int idx = blockIdx.x * 256 + threadIdx.x;
   if (idx >= CIN * 121) return;
-  const int c = idx % CIN, u = (idx / CIN) % 11, v = idx / CIN / 11;
-  const float val = flip ? w[((long)c * 11 + (10 - u)) * 11 + (10 - v)] : w[((long)c * 11 + u) * 11 + v];
-  out[idx] = from_f32<T>(val);
+  out[idx] = from_f32<T>(pack_last_val(w, idx, CIN, flip));
+}
+
+// Every packed operand of the paper's network (the three forward layers, the three
+// data-gradient operators) and the copies of the three bias tensors, in one launch:
+// element ranges follow each other in the order of PaperPack's fields.
+template <typename T>
+__global__ void pack_paper_kernel(PaperPack pk) {
+  long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  const long n1 = 11L * 2 * 64 * 8, n2 = 64L * 32 * 121, n3 = 32L * 121, n1f = 11L * 64 * 8, n2f = n2, n3f = 64L * 121;
+  if (idx < n1) { ((T *)pk.wp1)[idx] = from_f32<T>(pack_first_val(pk.w[0], (int)idx, 64, 0)); return; }
+  idx -= n1;
+  if (idx < n2) { ((T *)pk.wp2)[idx] = from_f32<T>(pack_mid_val(pk.w[1], idx, 64, 32, 0)); return; }
+  idx -= n2;
+  if (idx < n3) { ((T *)pk.wp3)[idx] = from_f32<T>(pack_last_val(pk.w[2], (int)idx, 32, 0)); return; }
+  idx -= n3;
+  if (idx < n1f) { ((T *)pk.wp3f)[idx] = from_f32<T>(pack_first_val(pk.w[2], (int)idx, 32, 1)); return; }
+  idx -= n1f;
+  if (idx < n2f) { ((T *)pk.wp2f)[idx] = from_f32<T>(pack_mid_val(pk.w[1], idx, 32, 64, 1)); return; }
+  idx -= n2f;
+  if (idx < n3f) { ((T *)pk.wp1f)[idx] = from_f32<T>(pack_last_val(pk.w[0], (int)idx, 64, 1)); return; }
+  idx -= n3f;
+#pragma unroll
+  for (int l = 0; l < 3; ++l) {
+    if (idx < pk.bn[l]) { pk.bp[l][idx] = pk.b[l][idx]; return; }
+    idx -= pk.bn[l];
+  }
+}
+long pack_paper_count(const PaperPack &pk) {
+  return 11L * 2 * 64 * 8 + 2 * 64L * 32 * 121 + 32L * 121 + 11L * 64 * 8 + 64L * 121 + pk.bn[0] + pk.bn[1] + pk.bn[2];
+}
+hipError_t pack_paper(const PaperPack &pk, int prec, hipStream_t s) {
+  const long n = pack_paper_count(pk);
+  if (prec == 1) pack_paper_kernel<bf16><<<GRID1(n), 0, s>>>(pk);
+  else pack_paper_kernel<float><<<GRID1(n), 0, s>>>(pk);
+  return hipGetLastError();
 }
 
 // per-pixel bias [C][H][W] -> [H][W][C]
@@ -373,12 +412,20 @@ __global__ __launch_bounds__(256) void image_stats_kernel(const TX *__restrict__
 }
 
 // L = (1/B) sum_b sse_b, summed in image order
-__global__ void loss_sum_kernel(const double *__restrict__ stats, int B, double *__restrict__ loss) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int b = 0; b < B; ++b) s += stats[b * 4];
-    *loss = s / B;
+// loss = (1/B) sum_b stats[b][0]: thread t sums images t, t+256, ... in order, then a
+// fixed pairwise tree over the 256 partial sums (the same result on every run)
+__global__ __launch_bounds__(256) void loss_sum_kernel(const double *__restrict__ stats, int B, double *__restrict__ loss) {
+  __shared__ double part[256];
+  const int t = threadIdx.x;
+  double sum = 0.0;
+  for (int b = t; b < B; b += 256) sum += stats[(long)b * 4];
+  part[t] = sum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (t < w) part[t] += part[t + w];
+    __syncthreads();
   }
+  if (t == 0) *loss = part[0] / B;
 }
 
 hipError_t image_stats_f32(const float *xh, const float *x, int B, int N, double *stats, float *g,
@@ -394,7 +441,7 @@ hipError_t image_stats_f64(const double *xh, const float *x, int B, int N, doubl
   return hipGetLastError();
 }
 hipError_t loss_sum(const double *stats, int B, double *loss, hipStream_t s) {
-  loss_sum_kernel<<<1, 64, 0, s>>>(stats, B, loss);
+  loss_sum_kernel<<<1, 256, 0, s>>>(stats, B, loss);
   return hipGetLastError();
 }
 
@@ -435,22 +482,47 @@ template hipError_t unpack_act<bf16>(const bf16 *, ActView, float *, int, hipStr
 
 // ------------------------------------------------------------------ Adam
 // theta -= lr * mhat / (sqrt(vhat) + eps), mhat = m / c1, vhat = v / c2
+DSI_INLINE float adam_one(float &th, float gi, float &m, float &v, float lr, float b1, float b2, float eps, float c1,
+                          float c2) {
+  const float mi = b1 * m + (1.0f - b1) * gi;
+  const float vi = b2 * v + (1.0f - b2) * gi * gi;
+  m = mi;
+  v = vi;
+  th -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  return th;
+}
 template <typename TG>
 __global__ void adam_kernel(float *__restrict__ th, const TG *__restrict__ g, float *__restrict__ m,
                             float *__restrict__ v, long n, float lr, float b1, float b2, float eps,
                             float c1, float c2) {
   const long idx = (long)blockIdx.x * 256 + threadIdx.x;
   if (idx >= n) return;
-  const float gi = (float)g[idx];
-  const float mi = b1 * m[idx] + (1.0f - b1) * gi;
-  const float vi = b2 * v[idx] + (1.0f - b2) * gi * gi;
-  m[idx] = mi;
-  v[idx] = vi;
-  th[idx] -= lr * (mi / c1) / (sqrtf(vi / c2) + eps);
+  adam_one(th[idx], (float)g[idx], m[idx], v[idx], lr, b1, b2, eps, c1, c2);
 }
 hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s) {
   if (n > 0) adam_kernel<float><<<GRID1(n), 0, s>>>(th, g, m, v, n, lr, b1, b2, eps, c1, c2);
+  return hipGetLastError();
+}
+// Several tensors in one launch: tensor k owns the flat range [start[k], start[k+1]); its
+// updated values are also written to mirror (when given), the network's own copy.
+__global__ void adam_multi_kernel(AdamMulti a, float lr, float b1, float b2, float eps, float c1, float c2) {
+  long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  int k = 0;
+  while (k < a.nseg && idx >= a.seg[k].n) {
+    idx -= a.seg[k].n;
+    ++k;
+  }
+  if (k >= a.nseg) return;
+  const AdamSeg &sg = a.seg[k];
+  const float t = adam_one(sg.th[idx], sg.g[idx], sg.m[idx], sg.v[idx], lr, b1, b2, eps, c1, c2);
+  if (sg.mirror) sg.mirror[idx] = t;
+}
+hipError_t adam_multi(const AdamMulti &a, float lr, float b1, float b2, float eps, float c1, float c2,
+                      hipStream_t s) {
+  long n = 0;
+  for (int k = 0; k < a.nseg; ++k) n += a.seg[k].n;
+  if (n > 0) adam_multi_kernel<<<GRID1(n), 0, s>>>(a, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
 
