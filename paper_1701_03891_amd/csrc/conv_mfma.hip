@@ -74,6 +74,12 @@ template <> DSI_INLINE void store4<bf16>(bf16 *dst, float a, float b, float c, f
 typedef float f32x2 __attribute__((ext_vector_type(2)));
 typedef __bf16 bf16x2 __attribute__((ext_vector_type(2)));
 typedef short s16x2 __attribute__((ext_vector_type(2)));
+DSI_INLINE i32x2 pack4_bf16_floor(float a, float b, float c, float d, s16x2 floor) {
+  const s16x2 lo = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2{a, b}), bf16x2));
+  const s16x2 hi = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2{c, d}), bf16x2));
+  return i32x2{__builtin_bit_cast(int, __builtin_elementwise_max(lo, floor)),
+               __builtin_bit_cast(int, __builtin_elementwise_max(hi, floor))};
+}
 DSI_INLINE void store4_bf16_floor(bf16 *dst, float a, float b, float c, float d, s16x2 floor) {
   const s16x2 lo = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2{a, b}), bf16x2));
   const s16x2 hi = __builtin_bit_cast(s16x2, __builtin_convertvector((f32x2{c, d}), bf16x2));
@@ -310,20 +316,21 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     const int gi = bi0 + wave * ROWS + i;
-    if (gi >= H || gj >= W) continue;
+    if (gi >= H || gj >= W) continue;   // (the lanes px and px + 32 of a pixel together)
 #pragma unroll
-    for (int c = 0; c < NCT; ++c)
+    for (int c = 0; c < NCT; ++c) {
+      float vals[4][4];
+      long o[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         const int co0 = c * 32 + 8 * q + 4 * h;
-        const long o = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
-        float vals[4];
+        o[q] = ((((long)img * (COUT / 16) + (co0 >> 4)) * H + gi) * W + gj) * 16 + (co0 & 15);
 #pragma unroll
-        for (int e = 0; e < 4; ++e) vals[e] = acc[i][c][4 * q + e] * oscale;
+        for (int e = 0; e < 4; ++e) vals[q][e] = acc[i][c][4 * q + e] * oscale;
         if constexpr (PREBIAS) {
 #pragma unroll
           for (int e = 0; e < 4; ++e)
-            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+            if (relu) vals[q][e] = fmaxf(vals[q][e], 0.0f);
         } else if constexpr (EPI == EPI_BIAS) {
           float bv[4];
           if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
@@ -334,17 +341,38 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
           }
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
-            vals[e] += bv[e];
-            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+            vals[q][e] += bv[e];
+            if (relu) vals[q][e] = fmaxf(vals[q][e], 0.0f);
           }
         } else {
           float mv[4];
-          load4f<T>(mask + o, mv);
+          load4f<T>(mask + o[q], mv);
 #pragma unroll
-          for (int e = 0; e < 4; ++e) vals[e] = mv[e] > 0.0f ? vals[e] : 0.0f;
+          for (int e = 0; e < 4; ++e) vals[q][e] = mv[e] > 0.0f ? vals[q][e] : 0.0f;
         }
-        store4<TO>(out + o, vals[0], vals[1], vals[2], vals[3]);
       }
+      if constexpr (sizeof(TO) == 2) {
+        // lane h holds channels 4h.. (q even) and 8 + 4h.. (q odd) of a 16-channel slice;
+        // one lane swap leaves it channels 8h .. 8h + 7, stored as one 16-byte unit
+#pragma unroll
+        for (int qp = 0; qp < 2; ++qp) {
+          const s16x2 none = {-32768, -32768};
+          i32x2 pa = pack4_bf16_floor(vals[2 * qp][0], vals[2 * qp][1], vals[2 * qp][2], vals[2 * qp][3], none);
+          i32x2 pb = pack4_bf16_floor(vals[2 * qp + 1][0], vals[2 * qp + 1][1], vals[2 * qp + 1][2],
+                                      vals[2 * qp + 1][3], none);
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const auto sw = __builtin_amdgcn_permlane32_swap((unsigned)pa[k], (unsigned)pb[k], false, false);
+            pa[k] = (int)sw[0];
+            pb[k] = (int)sw[1];
+          }
+          *reinterpret_cast<i32x4 *>(out + o[2 * qp] + 4 * h) = i32x4{pa[0], pa[1], pb[0], pb[1]};
+        }
+      } else {
+#pragma unroll
+        for (int q = 0; q < 4; ++q) store4<TO>(out + o[q], vals[q][0], vals[q][1], vals[q][2], vals[q][3]);
+      }
+    }
   }
 }
 
@@ -553,7 +581,73 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         }
       }
     }
-    if (!live) continue;
+    if (!live) continue;   // (the lanes px and px + 32 of a pixel are live together)
+    if constexpr (sizeof(TO) == 2) {
+      // Lane (px, h) holds channels 4h..4h+3 (q even) and 8+4h..11+4h (q odd) of each
+      // 16-channel slice.  One swap of lanes 32..63 of the first group with lanes 0..31
+      // of the second leaves lane h with channels 8h..8h+7, so each lane stores 16
+      // bytes and a wave writes 32 whole pixels (1 KiB contiguous) per slice.
+#pragma unroll
+      for (int c = 0; c < NCT; ++c)
+#pragma unroll
+        for (int qp = 0; qp < 2; ++qp) {
+          float va[4], vb[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            va[e] = acc[c][8 * qp + e];
+            vb[e] = acc[c][8 * qp + 4 + e];
+            if constexpr (EPI == EPI_BIAS) {
+              va[e] += bv[c][2 * qp][e];
+              vb[e] += bv[c][2 * qp + 1][e];
+            } else {
+              va[e] = mv[c][2 * qp][e] > 0.0f ? va[e] : 0.0f;
+              vb[e] = mv[c][2 * qp + 1][e] > 0.0f ? vb[e] : 0.0f;
+            }
+          }
+          const s16x2 fl = EPI == EPI_BIAS ? floor : s16x2{-32768, -32768};
+          i32x2 pa = pack4_bf16_floor(va[0], va[1], va[2], va[3], fl);
+          i32x2 pb = pack4_bf16_floor(vb[0], vb[1], vb[2], vb[3], fl);
+#pragma unroll
+          for (int k = 0; k < 2; ++k) {
+            const auto sw = __builtin_amdgcn_permlane32_swap((unsigned)pa[k], (unsigned)pb[k], false, false);
+            pa[k] = (int)sw[0];
+            pb[k] = (int)sw[1];
+          }
+          // slice 2c + qp, channels 8h.. of the pixel: the q-even group's offset plus 4h
+          *reinterpret_cast<i32x4 *>(oimg + ooff[c][2 * qp] + 4 * h) = i32x4{pa[0], pa[1], pb[0], pb[1]};
+        }
+      continue;
+    }
+    if constexpr (sizeof(TO) == 1 && NCT == 2 && EPI == EPI_BIAS) {
+      // FP8 codes, 64-channel pixels: lane (px, h) holds channels 32c + 8q + 4h .. +3.
+      // Swapping lanes 32..63 of the c = 0 groups with lanes 0..31 of the c = 1 groups
+      // leaves lane h with channels 32h .. 32h + 31: 32 bytes, two 16-byte stores.
+      int code[2][4];
+#pragma unroll
+      for (int c = 0; c < 2; ++c)
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          float vals[4];
+#pragma unroll
+          for (int e = 0; e < 4; ++e) {
+            vals[e] = acc[c][4 * q + e] + bv[c][q][e];
+            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+            vals[e] = fminf(fmaxf(vals[e] * oscale, -448.0f), 448.0f);
+          }
+          const int lo = __builtin_amdgcn_cvt_pk_fp8_f32(vals[0], vals[1], 0, false);
+          code[c][q] = __builtin_amdgcn_cvt_pk_fp8_f32(vals[2], vals[3], lo, true);
+        }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        const auto sw = __builtin_amdgcn_permlane32_swap((unsigned)code[0][q], (unsigned)code[1][q], false, false);
+        code[0][q] = (int)sw[0];
+        code[1][q] = (int)sw[1];
+      }
+      TO *dst = oimg + ooff[0][0] + 28 * h;   // channel 32h of the pixel (ooff[0][0] points at 4h)
+      *reinterpret_cast<i32x4 *>(dst) = i32x4{code[0][0], code[1][0], code[0][1], code[1][1]};
+      *reinterpret_cast<i32x4 *>(dst + 16) = i32x4{code[0][2], code[1][2], code[0][3], code[1][3]};
+      continue;
+    }
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
@@ -564,14 +658,9 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         for (int e = 0; e < 4; ++e) vals[e] = acc[c][4 * q + e];
         if constexpr (EPI == EPI_BIAS) {
 #pragma unroll
-          for (int e = 0; e < 4; ++e) vals[e] += bv[c][q][e];
-          if constexpr (sizeof(TO) == 2) {
-            store4_bf16_floor(reinterpret_cast<bf16 *>(dst), vals[0], vals[1], vals[2], vals[3], floor);
-            continue;
-          } else {
-#pragma unroll
-            for (int e = 0; e < 4; ++e)
-              if (relu) vals[e] = fmaxf(vals[e], 0.0f);
+          for (int e = 0; e < 4; ++e) {
+            vals[e] += bv[c][q][e];
+            if (relu) vals[e] = fmaxf(vals[e], 0.0f);
           }
         } else {
 #pragma unroll
