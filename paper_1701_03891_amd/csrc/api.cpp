@@ -106,7 +106,7 @@ struct dsi_net {
   void *b[DSI_MAX_LAYERS] = {};
   // paper path
   void *wp1 = nullptr, *wp2 = nullptr, *wp3 = nullptr;  // packed (compute precision)
-  float *bp[3] = {};                                     // fp32 biases (layout of dsi_params)
+  float *bp[3] = {};  // fp32 biases: dsi_params layout; layer 2 per-pixel in fragment order [H][W][32]
   void *wp3f = nullptr, *wp2f = nullptr, *wp1f = nullptr;  // packed data-gradient operators
   float w_scale_fc = 1.0f, w_scale_2 = 1.0f;              // FP8 per-tensor weight scales
   unsigned *amax_dev = nullptr;                            // FP8: device scratch for amax
@@ -262,10 +262,11 @@ dsi_status pack_params_fp8(dsi_net *n, const dsi_params *p, hipStream_t s) {
   HIPCHK(dsi::pack_first(p->w[0], n->wp1, 64, 0, 1, s));
   HIPCHK(dsi::pack_mid_fp8(p->w[1], (u8 *)n->wp2, 1.0f / n->w_scale_2, s));
   HIPCHK(dsi::pack_last(p->w[2], n->wp3, 32, 0, 1, s));
+  // biases: layer 2's per-pixel bias in the conv2 epilogue's fragment order, the others
+  // planar [C][H][W] (their epilogues read them coalesced)
   for (int l = 0; l < 3; ++l) {
-    const int C = d.C[l + 1];
-    (void)C;  // per-pixel biases stay planar [C][H][W]: the epilogues read them coalesced
-    HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    if (l == 1 && d.bias_per_pixel) HIPCHK(dsi::pack_bias_frag(p->b[1], n->bp[1], 32, (long)N, s));
+    else HIPCHK(hipMemcpyAsync(n->bp[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
   }
   return DSI_OK;
 }
@@ -304,9 +305,10 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with
     return DSI_OK;
   }
   // forward operators, data-gradient operators (layer 3: 32 <- 1, layer 2: 64 <- 32,
-  // layer 1: 1 <- 64) and the biases (per-pixel biases stay planar [C][H][W]: the
-  // epilogues read them coalesced), in one launch
+  // layer 1: 1 <- 64) and the biases (layer 2's per-pixel bias in the conv2 epilogue's
+  // fragment order, the others planar [C][H][W]), in one launch
   dsi::PaperPack pk{};
+  pk.hw2 = d.bias_per_pixel ? (long)HW : 0;
   for (int l = 0; l < 3; ++l) {
     pk.w[l] = p->w[l];
     pk.b[l] = p->b[l];

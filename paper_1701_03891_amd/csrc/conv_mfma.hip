@@ -131,7 +131,9 @@ DSI_INLINE void stage_units(unsigned char *lds, int tid, F unit) {
 // in   [B][CIN/SC][H][W][SC]  (T; SC = 16 channels per slice, 64 for FP8)
 // wp   [CIN/SC][11 v][11 u][COUT/32][64 lanes][FE]  (T; FE = 8, 32 for FP8): lane l holds
 //      W[co = ct*32 + l%32][ci = cs*SC + (l/32)*FE + e][u][v]
-// EPI_BIAS: out = ReLU?(oscale * acc + bias); bias per pixel [COUT][H][W] or per channel [COUT] (fp32)
+// EPI_BIAS: out = ReLU?(oscale * acc + bias); bias per channel [COUT] or per pixel in fragment
+//      order [H][W][COUT/32][2][4][4] (fp32): position (c, h, q, e) of a pixel holds channel
+//      32c + 8q + 4h + e, so a lane's 16 values of one row are 64 contiguous bytes
 // EPI_MASK: out = acc * (mask > 0), mask in the output layout (backward through ReLU)
 // oscale dequantises FP8 products (weight scale x activation scale); 1 otherwise.
 // A block has WAVES waves stacked vertically (WAVES * ROWS output rows x 32 columns).
@@ -177,14 +179,15 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
-      for (int q = 0; q < 4; ++q)
-#pragma unroll
-        for (int e = 0; e < 4; ++e) {
-          const int co = c * 32 + 8 * q + 4 * h + e;
-          float b0v = 0.0f;
-          if (PREBIAS && live) b0v = bias_pp ? bias[((long)co * H + gi) * W + gj] : bias[co];
-          acc[i][c][4 * q + e] = b0v;
+      for (int q = 0; q < 4; ++q) {
+        f32x4 b4 = {0.0f, 0.0f, 0.0f, 0.0f};
+        if (PREBIAS && live) {
+          if (bias_pp) b4 = *reinterpret_cast<const f32x4 *>(bias + ((long)gi * W + gj) * COUT + c * 32 + h * 16 + q * 4);
+          else b4 = *reinterpret_cast<const f32x4 *>(bias + c * 32 + 8 * q + 4 * h);
         }
+#pragma unroll
+        for (int e = 0; e < 4; ++e) acc[i][c][4 * q + e] = b4[e];
+      }
   }
 
   // unit k of this thread (u = k NT + tid, [row][chunk][col] order) of slice sl, zero
@@ -333,12 +336,8 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
             if (relu) vals[q][e] = fmaxf(vals[q][e], 0.0f);
         } else if constexpr (EPI == EPI_BIAS) {
           float bv[4];
-          if (bias_pp) {  // planar [COUT][H][W]: consecutive lanes read consecutive pixels
-#pragma unroll
-            for (int e = 0; e < 4; ++e) bv[e] = bias[((long)(co0 + e) * H + gi) * W + gj];
-          } else {
-            load4f<float>(bias + co0, bv);
-          }
+          if (bias_pp) load4f<float>(bias + ((long)gi * W + gj) * COUT + c * 32 + h * 16 + q * 4, bv);
+          else load4f<float>(bias + co0, bv);
 #pragma unroll
           for (int e = 0; e < 4; ++e) {
             vals[q][e] += bv[e];

@@ -68,7 +68,10 @@ struct PaperPack {
   void *wp1, *wp2, *wp3;  // forward operands (T)
   void *wp3f, *wp2f, *wp1f;  // data-gradient operators (T)
   float *bp[3];           // the network's bias copies
+  long hw2;               // H * W: layer 2's per-pixel bias goes to fragment order; 0: plain copy
 };
+// per-pixel bias [C][HW] -> [HW][C/32][2][4][4] (the conv_mid epilogue's order)
+hipError_t pack_bias_frag(const float *b, float *out, int C, long HW, hipStream_t s);
 hipError_t pack_paper(const PaperPack &pk, int prec, hipStream_t s);
 hipError_t pack_bias_hwc(const float *b, float *out, int C, int HW, hipStream_t s);
 hipError_t cast_f32_f64(const float *in, double *out, long n, hipStream_t s);

@@ -72,6 +72,23 @@ __global__ void pack_last_kernel(const float *__restrict__ w, T *__restrict__ ou
   out[idx] = from_f32<T>(pack_last_val(w, idx, CIN, flip));
 }
 
+// Per-pixel bias [C][HW] -> fragment order [HW][C/32][2][4][4]: element idx = pix * C + pos
+// comes from channel 32c + 8q + 4h + e, (c, h, q, e) the digits of pos.
+DSI_INLINE long bias_frag_src(long idx, int C, long HW) {
+  const long pix = idx / C;
+  const int pos = (int)(idx % C), r = pos % 32;
+  const int ch = 32 * (pos / 32) + 8 * ((r / 4) % 4) + 4 * (r / 16) + r % 4;
+  return (long)ch * HW + pix;
+}
+__global__ void pack_bias_frag_kernel(const float *__restrict__ b, float *__restrict__ out, int C, long HW) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx < (long)C * HW) out[idx] = b[bias_frag_src(idx, C, HW)];
+}
+hipError_t pack_bias_frag(const float *b, float *out, int C, long HW, hipStream_t s) {
+  pack_bias_frag_kernel<<<GRID1((long)C * HW), 0, s>>>(b, out, C, HW);
+  return hipGetLastError();
+}
+
 // Every packed operand of the paper's network (the three forward layers, the three
 // data-gradient operators) and the copies of the three bias tensors, in one launch:
 // element ranges follow each other in the order of PaperPack's fields.
@@ -93,7 +110,10 @@ __global__ void pack_paper_kernel(PaperPack pk) {
   idx -= n3f;
 #pragma unroll
   for (int l = 0; l < 3; ++l) {
-    if (idx < pk.bn[l]) { pk.bp[l][idx] = pk.b[l][idx]; return; }
+    if (idx < pk.bn[l]) {
+      pk.bp[l][idx] = pk.b[l][l == 1 && pk.hw2 ? bias_frag_src(idx, 32, pk.hw2) : idx];
+      return;
+    }
     idx -= pk.bn[l];
   }
 }
