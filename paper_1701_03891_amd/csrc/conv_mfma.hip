@@ -10,15 +10,17 @@
 //   ROWS output rows x 32 columns x Cout channels.  For each 16-channel slice
 //   and horizontal tap v it keeps the 11 vertical-tap weight fragments in
 //   registers and walks the ROWS+10 input rows of its halo once: every
-//   activation fragment read from LDS feeds up to 11 MFMAs (one per output
+//   activation fragment read from LDS feeds up to ROWS MFMAs (one per output
 //   row it reaches), so LDS traffic is ~1/5 of a naive implicit GEMM.
 //   MFMA: A = weights (32 out-channels x 16 in-channels), B = activations
 //   (16 in-channels x 32 pixels), D = 32 out-channels x 32 pixels.
 // conv_first (Cin = 1 -> 64): K = taps; one MFMA k-step per filter row u,
 //   its 16 K slots holding taps v = 0..10 (5 zero slots), gathered from a
 //   small LDS tile of the proxy image.
-// conv_last  (Cin = 32 -> 1): a degenerate GEMM (one output channel), done on
-//   the vector ALUs with packed bf16 dot products.
+// conv_last  (Cin = 32 -> 1): one output channel, a banded-Toeplitz GEMM on
+//   16x16 MFMAs (output rows as N, the weight band built by lane shifts).
+#include <algorithm>
+
 #include "common.h"
 #include "internal.h"
 
@@ -148,7 +150,7 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
                                                               const float *__restrict__ bias, int bias_pp, int relu,
                                                               const T *__restrict__ mask, TO *__restrict__ out,
                                                               int H, int W, int tiles_w, int tiles_per_img,
-                                                              float oscale) {
+                                                              int ntiles, float oscale) {
   constexpr int NT = 64 * WAVES;
   constexpr int TH = WAVES * ROWS, TW = 32, LH = TH + 2 * RAD, LW = TW + 2 * RAD;
   constexpr int SC = slice_ch<T>();
@@ -163,13 +165,58 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   __shared__ __attribute__((aligned(16))) unsigned char lds[(ASYNC ? 2 : 1) * BUF];
 
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, px = lane & 31;
-  // tiles of one image (whose halos overlap) on one XCD, side by side in time
-  const int tl = xcd_logical(blockIdx.x, gridDim.x);
-  const int img = tl / tiles_per_img, t = tl % tiles_per_img;
-  const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
+  // A block runs tiles tl, tl + G, ... (G = the grid; one tile per block unless the grid
+  // is smaller than the tile count).  The tiles of one image (whose halos overlap) sit on
+  // one XCD, side by side in time.
+  const int G = gridDim.x;
+  int tl = xcd_logical(blockIdx.x, G);
+  auto tile_at = [&](int t_, int &img_, int &bi0_, int &bj0_) {
+    img_ = t_ / tiles_per_img;
+    const int r_ = t_ % tiles_per_img;
+    bi0_ = (r_ / tiles_w) * TH;
+    bj0_ = (r_ % tiles_w) * TW;
+  };
+  int img, bi0, bj0;
+  tile_at(tl, img, bi0, bj0);
 
-  // With prefetched staging the accumulators start from the bias (loaded now, while the
-  // first slice is staged), so the epilogue issues no loads.
+  // unit k of this thread (u = k NT + tid, [row][chunk][col] order) of slice sl of the
+  // tile at (timg, ti0, tj0), zero outside the image
+  auto unit_load = [&](int timg, int ti0, int tj0, int sl, int k) -> i32x4 {
+    const int u = k * NT + tid;
+    const int row = u / (CH16 * LW), rem = u - row * (CH16 * LW);
+    const int chunk = rem / LW, col = rem - chunk * LW;
+    const int gi = ti0 - RAD + row, gj = tj0 - RAD + col;
+    i32x4 val = {0, 0, 0, 0};
+    if (k < NPF && u < NU && gi >= 0 && gi < H && gj >= 0 && gj < W)
+      val = *reinterpret_cast<const i32x4 *>(in + (long)(timg * NCS + sl) * H * W * SC + ((long)gi * W + gj) * SC +
+                                             chunk * 8);
+    return val;
+  };
+  auto unit_store = [&](unsigned char *b, int k, const i32x4 &val) {
+    if (k < NPF && k * NT + tid < NU) *reinterpret_cast<i32x4 *>(b + (k * NT + tid) * 16) = val;
+  };
+  if constexpr (ASYNC) {
+    i32x4 pf[NPF];
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) pf[k] = unit_load(img, bi0, bj0, 0, k);
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) unit_store(lds, k, pf[k]);
+    __syncthreads();
+  }
+  int gsl = 0;   // slices computed so far by this block: their buffers alternate
+  // weight fragments of the current and the next tap column (with prefetching, the
+  // last column of a slice loads the next slice's first, so they outlive a tile)
+  Frag8<T> wf[KT][NCT], wn[KT][NCT];
+
+  for (;;) {   // over the block's tiles (one pass without prefetching)
+  tile_at(tl, img, bi0, bj0);
+  // the block's next tile: its first slice is prefetched during this tile's last one
+  const bool has_next = tl + G < ntiles;
+  int nimg = img, ni0 = bi0, nj0 = bj0;
+  if (has_next) tile_at(tl + G, nimg, ni0, nj0);
+
+  // With prefetched staging the accumulators start from the bias, so the epilogue
+  // issues no loads.
   constexpr bool PREBIAS = ASYNC && EPI == EPI_BIAS;
   f32x16 acc[ROWS][NCT];
 #pragma unroll
@@ -190,31 +237,6 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
       }
   }
 
-  // unit k of this thread (u = k NT + tid, [row][chunk][col] order) of slice sl, zero
-  // outside the image
-  auto unit_load = [&](int sl, int k) -> i32x4 {
-    const int u = k * NT + tid;
-    const int row = u / (CH16 * LW), rem = u - row * (CH16 * LW);
-    const int chunk = rem / LW, col = rem - chunk * LW;
-    const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-    i32x4 val = {0, 0, 0, 0};
-    if (k < NPF && u < NU && gi >= 0 && gi < H && gj >= 0 && gj < W)
-      val = *reinterpret_cast<const i32x4 *>(in + (long)(img * NCS + sl) * H * W * SC + ((long)gi * W + gj) * SC +
-                                             chunk * 8);
-    return val;
-  };
-  auto unit_store = [&](unsigned char *b, int k, const i32x4 &val) {
-    if (k < NPF && k * NT + tid < NU) *reinterpret_cast<i32x4 *>(b + (k * NT + tid) * 16) = val;
-  };
-  if constexpr (ASYNC) {
-    i32x4 pf[NPF];
-#pragma unroll
-    for (int k = 0; k < NPF; ++k) pf[k] = unit_load(0, k);
-#pragma unroll
-    for (int k = 0; k < NPF; ++k) unit_store(lds, k, pf[k]);
-    __syncthreads();
-  }
-
   for (int cs = 0; cs < NCS; ++cs) {
    if constexpr (!ASYNC) {
     __syncthreads();  // previous slice fully consumed
@@ -233,14 +255,21 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
     });
     __syncthreads();
    }
-    const unsigned char *buf = lds + (ASYNC ? (cs & 1) * BUF : 0);
+    const unsigned char *buf = lds + (ASYNC ? (gsl & 1) * BUF : 0);
     const T *wcs = wp + (long)cs * KT * KT * NCT * 64 * FE + lane * FE;
-    Frag8<T> wf[KT][NCT], wn[KT][NCT];
+    // (with prefetching, the previous slice's last column already loaded this slice's
+    // first weight column into wf)
+    if (!ASYNC || gsl == 0) {
 #pragma unroll
-    for (int u = 0; u < KT; ++u)
+      for (int u = 0; u < KT; ++u)
 #pragma unroll
-      for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + (u * NCT + c) * 64 * FE);
-    unsigned char *nbuf = lds + ((cs + 1) & 1) * BUF;  // next slice's buffer (ASYNC), unread now
+        for (int c = 0; c < NCT; ++c) wf[u][c] = frag_load<T>(wcs + (u * NCT + c) * 64 * FE);
+    }
+    unsigned char *nbuf = lds + ((gsl + 1) & 1) * BUF;  // next slice's buffer (ASYNC), unread now
+    // the slice prefetched during this one: the tile's next, or the next tile's first
+    const bool pf_any = cs + 1 < NCS || has_next;
+    const int pf_img = cs + 1 < NCS ? img : nimg, pf_i0 = cs + 1 < NCS ? bi0 : ni0;
+    const int pf_j0 = cs + 1 < NCS ? bj0 : nj0, pf_sl = cs + 1 < NCS ? cs + 1 : 0;
     i32x4 pa0 = {0, 0, 0, 0}, pa1 = {0, 0, 0, 0};     // units loaded one column ago
     int pk = -1;                                       // their first unit index
     const unsigned char *lrow0 = buf + (wave * ROWS * CH16 + h * (CH16 / 2)) * PLANE + px * 16;
@@ -263,18 +292,24 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
         for (int u = 0; u < KT; ++u)
 #pragma unroll
           for (int c = 0; c < NCT; ++c) wn[u][c] = frag_load<T>(wcs + (((v + 1) * KT + u) * NCT + c) * 64 * FE);
+      } else if (ASYNC && pf_any) {   // the next slice's first column
+        const T *wnx = wp + (long)pf_sl * KT * KT * NCT * 64 * FE + lane * FE;
+#pragma unroll
+        for (int u = 0; u < KT; ++u)
+#pragma unroll
+          for (int c = 0; c < NCT; ++c) wn[u][c] = frag_load<T>(wnx + (u * NCT + c) * 64 * FE);
       }
       if constexpr (ASYNC) {
         static_assert(NPF <= 2 * (KT - 1), "two units per column must cover the slice");
-        if (cs + 1 < NCS) {
+        if (pf_any) {
           if (pk >= 0) {
             unit_store(nbuf, pk, pa0);
             unit_store(nbuf, pk + 1, pa1);
           }
           pk = -1;
           if (2 * v < NPF) {
-            pa0 = unit_load(cs + 1, 2 * v);
-            pa1 = unit_load(cs + 1, 2 * v + 1);
+            pa0 = unit_load(pf_img, pf_i0, pf_j0, pf_sl, 2 * v);
+            pa1 = unit_load(pf_img, pf_i0, pf_j0, pf_sl, 2 * v + 1);
             pk = 2 * v;
           }
         }
@@ -306,12 +341,13 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
         for (int c = 0; c < NCT; ++c) wf[u][c] = wn[u][c];
     }
     if constexpr (ASYNC) {
-      if (cs + 1 < NCS && pk >= 0) {
+      if (pf_any && pk >= 0) {
         unit_store(nbuf, pk, pa0);
         unit_store(nbuf, pk + 1, pa1);
       }
       __syncthreads();  // the next slice is in place and every wave is done with this one
     }
+    ++gsl;
   }
 
   // epilogue: lane holds pixel (row i, col px), channels ct*32 + 8q + 4h + e
@@ -373,6 +409,10 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
       }
     }
   }
+  if constexpr (!ASYNC) break;
+  tl += G;
+  if (tl >= ntiles) break;
+  }  // tiles
 }
 
 // =================================================================== conv_first
@@ -943,6 +983,18 @@ template <> DSI_INLINE void mma16<float>(const Frag8<float> &a, const Frag8<floa
 }
 
 // ==================================================================== launchers
+// compute units of the current device (cached per device)
+static int cu_count() {
+  static int cached[64] = {};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (cached[dev] <= 0) {
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || n <= 0) n = 256;
+    cached[dev] = n;
+  }
+  return cached[dev];
+}
 static inline void tiles(int H, int W, int TH, int TW, int &tw, int &tpi) {
   tw = (W + TW - 1) / TW;
   tpi = tw * ((H + TH - 1) / TH);
@@ -976,8 +1028,15 @@ hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, in
   constexpr bool ASYNC = sizeof(T) == 2 && COUT == 32;
   int tw, tpi;
   tiles(H, W, WAVES * ROWS, 32, tw, tpi);
-  conv_mid_kernel<T, CIN, COUT, ROWS, WAVES, EPI, TO, ASYNC>
-      <<<B * tpi, 64 * WAVES, 0, s>>>(in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, oscale);
+  const long ntiles = (long)B * tpi;
+  if (ntiles >= (1L << 31)) return hipErrorInvalidValue;
+  // prefetching kernel: one block per CU (its LDS allows no more), each running every
+  // G-th tile and staging the next tile's first slice during its last; otherwise one
+  // block per tile
+  long grid = ntiles;
+  if (ASYNC) grid = std::min(grid, (long)cu_count());
+  conv_mid_kernel<T, CIN, COUT, ROWS, WAVES, EPI, TO, ASYNC><<<(unsigned)grid, 64 * WAVES, 0, s>>>(
+      in, wp, bias, bias_pp, relu, mask, out, H, W, tw, tpi, (int)ntiles, oscale);
   return hipGetLastError();
 }
 
