@@ -305,7 +305,14 @@ def cpu_baseline(phi, x, prm, y_host, xhs, n_img, c4=None, c1=None):
     dt = time.perf_counter() - t0
     xs = x[:n_img]
     ps64 = oracle.psnr(ref, xs)
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            model = next((ln.split(":", 1)[1].strip() for ln in f if ln.startswith("model name")), model)
+    except OSError:
+        pass
     out = {"value": n_img / dt, "unit": "images/s", "cores": threads, "kind": "oracle",
+           "host": {"cpu_model": model, "logical_cpus": os.cpu_count()},
            "sample": f"{n_img} of the 256 images of the batch (64x64, M=1024), FP64 C oracle, "
                      f"{dt:.1f} s on {threads} threads",
            "single_core": {"value": 4 / dt1, "unit": "images/s", "sample": f"4 images, {dt1:.1f} s on 1 thread"}}
