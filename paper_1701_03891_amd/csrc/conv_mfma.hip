@@ -863,12 +863,13 @@ DSI_INLINE int band_shift(int x, int S) {
   }
 }
 
-// BF16 variant: one 16-channel slice per pass and K = 32 packing two horizontal
-// taps (v = 2p, 2p + 1) x 16 channels, so a pass holds only 32 bytes per pixel
-// in LDS (62 KiB per block, two blocks per CU) and a tap pair costs one MFMA.
-// Lane group g = l/16 holds K slots 8g .. 8g+7: channels 8(g&1) .. +7 of tap
-// v = 2p + (g>>1).  The sixth pair's second tap (v = 11) has a zero weight band;
-// its activations come from one extra LDS column that is zero-filled.
+// BF16 variant: one 8-channel half-slice per pass and K = 32 packing four horizontal
+// taps (v = 4p .. 4p + 3) x 8 channels, so a pass holds 16 bytes per pixel in LDS (31 KiB
+// per 16 x 64 tile).  Two pass buffers: while one pass walks, each thread loads its units
+// of the next pass into registers and stores them into the other buffer at the end (two
+// blocks per CU still fit).  Lane group g = l/16 holds K slots 8g .. 8g+7: channels
+// 0 .. 7 of the pass at tap v = 4p + g.  The third quad's last tap (v = 11) has a zero
+// weight band; its activations come from one extra LDS column that is zero-filled.
 // wt [11 v][11 u][CIN] (bf16), staged in LDS with a zero v = 11 plane.
 template <int CIN>
 __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wt,
@@ -876,65 +877,90 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
                                                              float *__restrict__ out, int H, int W, int tiles_w,
                                                              int tiles_per_img) {
   constexpr int TH = 16, TW = 64, LH = TH + 2 * RAD, LW = TW + 2 * RAD + 1;
-  constexpr int NP = (KT + 1) / 2;          // tap pairs
-  constexpr int ROWB = LW * 32;             // bytes per LDS row: pixels of two 8-channel units
-  constexpr int NS = CIN / 16;              // 16-channel slices = passes
-  __shared__ __attribute__((aligned(16))) unsigned char lds[LH * ROWB];
+  constexpr int NQ = (KT + 3) / 4;          // tap quads
+  constexpr int ROWB = LW * 16;             // bytes per LDS row: 8-channel pixels
+  constexpr int BUF = LH * ROWB;            // bytes per pass buffer
+  constexpr int NS = CIN / 8;               // 8-channel passes
+  constexpr int NU = LH * LW;               // 16-byte units per pass
+  constexpr int NPF = (NU + 255) / 256;     // units per thread per pass
+  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
   __shared__ __attribute__((aligned(16))) bf16 wl[(KT + 1) * KT * CIN];
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
   // tiles of one image (whose halos overlap) on one XCD, side by side in time
   const int tl = xcd_logical(blockIdx.x, gridDim.x);
   const int img = tl / tiles_per_img, t = tl % tiles_per_img;
   const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
+  // unit k of this thread in pass sl: pixel (row, col) of the tile, channels 8 sl .. 8 sl + 7
+  // (zero outside the image and in the last column)
+  auto unit_load = [&](int sl, int k) -> i32x4 {
+    const int u = tid + 256 * k;
+    const int row = u / LW, col = u - row * LW;
+    const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
+    i32x4 v = {0, 0, 0, 0};
+    if (u < NU && col < LW - 1 && gi >= 0 && gi < H && gj >= 0 && gj < W)
+      v = *reinterpret_cast<const i32x4 *>(in + (((long)img * (CIN / 16) + sl / 2) * H * W + (long)gi * W + gj) * 16 +
+                                           (sl & 1) * 8);
+    return v;
+  };
   {
-    // weights as 16-byte units, every load issued before the stores (the v = 11 plane zero)
+    // weights as 16-byte units, every load issued before the stores (the v = 11 plane zero);
+    // with them, the first pass
     constexpr int NWU = (KT + 1) * KT * CIN / 8, NWL = KT * KT * CIN / 8, NIT = (NWU + 255) / 256;
-    i32x4 wv[NIT];
+    i32x4 wv[NIT], pf[NPF];
 #pragma unroll
     for (int k = 0; k < NIT; ++k) {
       const int idx = tid + 256 * k;
       wv[k] = idx < NWL ? *reinterpret_cast<const i32x4 *>(wt + idx * 8) : i32x4{0, 0, 0, 0};
     }
 #pragma unroll
+    for (int k = 0; k < NPF; ++k) pf[k] = unit_load(0, k);
+#pragma unroll
     for (int k = 0; k < NIT; ++k)
       if (tid + 256 * k < NWU) *reinterpret_cast<i32x4 *>(wl + (tid + 256 * k) * 8) = wv[k];
-  }
-  f32x4 acc[NP];
 #pragma unroll
-  for (int p = 0; p < NP; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  // this lane's LDS column for tap pair 0 and its 8-channel plane
-  const unsigned char *abase = lds + (g & 1) * 16 + (wave * 16 + n + (g >> 1)) * 32;
+    for (int k = 0; k < NPF; ++k)
+      if (tid + 256 * k < NU) *reinterpret_cast<i32x4 *>(lds + (tid + 256 * k) * 16) = pf[k];
+    __syncthreads();
+  }
+  // this lane's outputs: row n, columns 4g .. 4g+3 of the wave's 16; their biases are
+  // loaded now, so the epilogue waits for nothing
+  const int go = bi0 + n, gj0 = bj0 + wave * 16 + 4 * g;
+  float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+  if (bias && go < H) {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (gj0 + e < W) bv[e] = bias_pp ? bias[(long)go * W + gj0 + e] : bias[0];
+  }
+  f32x4 acc[NQ];
+#pragma unroll
+  for (int p = 0; p < NQ; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
   for (int sl = 0; sl < NS; ++sl) {
-    __syncthreads();
-    const bf16 *src = in + (long)(img * NS + sl) * H * W * 16;
-    // unit idx = (pixel, 8-channel half) in LDS order: contiguous reads and stores
-    stage_units<LH * LW * 2, 256>(lds, tid, [&](int idx, int &loff) -> const void * {
-      const int q = idx & 1, pix = idx >> 1;
-      const int row = pix / LW, col = pix - row * LW;
-      const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-      loff = idx * 16;
-      if (col >= LW - 1 || gi < 0 || gi >= H || gj < 0 || gj >= W) return nullptr;
-      return src + ((long)gi * W + gj) * 16 + q * 8;
-    });
-    __syncthreads();
-    // Band operand of pair p at input row r: B[k][i] = W[c][u = r - i][v], zero outside
+    const unsigned char *buf = lds + (sl & 1) * BUF;
+    unsigned char *nbuf = lds + ((sl + 1) & 1) * BUF;   // unread during this pass
+    // the next pass's units, in flight during the walk
+    i32x4 pf[NPF];
+    const bool more = sl + 1 < NS;
+#pragma unroll
+    for (int k = 0; k < NPF; ++k) pf[k] = more ? unit_load(sl + 1, k) : i32x4{0, 0, 0, 0};
+    // Band operand of quad p at input row r: B[k][i] = W[c][u = r - i][v], zero outside
     // 0 <= u <= 10.  It is one register z[p] moved across lanes: lane n of each 16-lane
     // group holds W[u = 10 - n] (zero for n > 10), so B at row r is z shifted by 10 - r
     // lanes (DPP row_shl:10-r for r < 10, row_shr:r-10 for r > 10, zeros shifted in).
-    i32x4 z[NP];
-    const bf16 *whead = wl + (g >> 1) * KT * CIN + sl * 16 + 8 * (g & 1);
+    i32x4 z[NQ];
+    const bf16 *whead = wl + g * KT * CIN + sl * 8;
 #pragma unroll
-    for (int p = 0; p < NP; ++p) {
-      const i32x4 w = *reinterpret_cast<const i32x4 *>(whead + (2 * p * KT + KT - 1 - min(n, KT - 1)) * CIN);
+    for (int p = 0; p < NQ; ++p) {
+      const i32x4 w = *reinterpret_cast<const i32x4 *>(whead + (4 * p * KT + KT - 1 - min(n, KT - 1)) * CIN);
       z[p] = n < KT ? w : i32x4{0, 0, 0, 0};
     }
-    // The pass is one walk of LH x NP (row, tap pair) steps.  Each step's activation
+    // The pass is one walk of LH x NQ (row, tap quad) steps.  Each step's activation
     // fragment is read LA steps ahead, and a scheduling barrier after every step keeps the
     // reads there, so the LDS latency hides behind the MFMAs between.
-    constexpr int NST = LH * NP, LA = 4;
+    const unsigned char *abase = buf + (wave * 16 + n + g) * 16;   // this lane's pixel for quad 0
+    constexpr int NST = LH * NQ, LA = 4;
     auto afrag = [&](int st) {
       Frag8<bf16> a;
-      a.v = *reinterpret_cast<const bf16x8 *>(abase + (st / NP) * ROWB + 2 * (st % NP) * 32);
+      a.v = *reinterpret_cast<const bf16x8 *>(abase + (st / NQ) * ROWB + 4 * (st % NQ) * 16);
       return a;
     };
     Frag8<bf16> aq[LA];
@@ -943,8 +969,8 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
 #pragma unroll
     for (int r = 0; r < LH; ++r) {
 #pragma unroll
-      for (int p = 0; p < NP; ++p) {
-        const int st = r * NP + p;
+      for (int p = 0; p < NQ; ++p) {
+        const int st = r * NQ + p;
         const Frag8<bf16> a = aq[st % LA];
         if (st + LA < NST) aq[st % LA] = afrag(st + LA);
         i32x4 band;
@@ -956,21 +982,30 @@ __global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restr
         __builtin_amdgcn_sched_barrier(0);
       }
     }
+    if (more) {
+#pragma unroll
+      for (int k = 0; k < NPF; ++k)
+        if (tid + 256 * k < NU) *reinterpret_cast<i32x4 *>(nbuf + (tid + 256 * k) * 16) = pf[k];
+    }
+    __syncthreads();   // the next pass is in place and every wave is done with this one
   }
   f32x4 accs = acc[0];
 #pragma unroll
-  for (int p = 1; p < NP; ++p) accs += acc[p];
-  // lane holds output row n, columns 4g .. 4g+3 of the wave's 16
-  const int gi = bi0 + n;
-  if (gi >= H) return;
-  const int gj0 = bj0 + wave * 16 + 4 * g;
+  for (int p = 1; p < NQ; ++p) accs += acc[p];
+  if (go >= H) return;
+  float v[4];
 #pragma unroll
   for (int e = 0; e < 4; ++e) {
-    const int gj = gj0 + e;
-    if (gj >= W) break;
-    float v = accs[e];
-    if (bias) v += bias_pp ? bias[(long)gi * W + gj] : bias[0];
-    out[((long)img * H + gi) * W + gj] = relu ? fmaxf(v, 0.0f) : v;
+    v[e] = accs[e] + bv[e];
+    if (relu) v[e] = fmaxf(v[e], 0.0f);
+  }
+  float *dst = out + ((long)img * H + go) * W + gj0;
+  if (W % 4 == 0 && gj0 + 3 < W) {
+    *reinterpret_cast<f32x4 *>(dst) = f32x4{v[0], v[1], v[2], v[3]};
+  } else {
+#pragma unroll
+    for (int e = 0; e < 4; ++e)
+      if (gj0 + e < W) dst[e] = v[e];
   }
 }
 
