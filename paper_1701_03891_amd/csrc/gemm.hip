@@ -188,7 +188,7 @@ __global__ __launch_bounds__(256) void gemm_frag_kernel(const T *__restrict__ Xp
                                                         bf16 *__restrict__ C, long ldc, int Bn, int O, int KS,
                                                         float scale) {
   constexpr int FE = sizeof(T) == 1 ? 32 : 8;
-  constexpr int PF = sizeof(T) == 1 ? 4 : 8;
+  constexpr int PF = sizeof(T) == 1 ? 8 : 16;   // k-steps in flight: the loads are latency-bound
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int bt = blockIdx.y * 2 + (wave >> 1), ot = blockIdx.x * 2 + (wave & 1);
   if (bt * 32 >= Bn || ot * 32 >= O) return;
