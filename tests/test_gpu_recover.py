@@ -94,6 +94,19 @@ def test_recover_ragged_tiles(dsi, prec, bias_per_pixel):
     assert err.max() <= TOL[prec]
 
 
+def test_recover_uneven_tiles_per_block(dsi):
+    """BF16 conv2 runs one block per CU over every G-th tile: 40x48 images, batch 100 give
+    400 tiles, so some blocks run two tiles (prefetching the second's first slice) and
+    others one; every image is checked."""
+    P, ctx = dsi
+    case = make_case(40, 48, 500, 100, cfg_id=12, bias_std=0.05)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, "bf16")
+    err = relerr_per_image(got, ref)
+    print(f"uneven tiles bf16: max rel err {err.max():.3e}")
+    assert err.max() <= TOL["bf16"]
+
+
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
 def test_recover_image_smaller_than_filter(dsi, prec):
     """5x7 images, smaller than the 11x11 filters (taps reach the zero padding); M = 3; batch 2."""
