@@ -141,10 +141,12 @@ DSI_INLINE void stage_units(unsigned char *lds, int tid, F unit) {
 // A block has WAVES waves stacked vertically (WAVES * ROWS output rows x 32 columns).
 // The weight fragments of tap column v + 1 are loaded while tap column v computes.
 // ASYNC (BF16): two LDS slice buffers.  While slice cs computes, each thread loads its
-// units of slice cs+1, two per tap column right after that column's weight loads, and
-// stores them into the other buffer one column later, when they have long arrived
-// (loads retire in order, so no wait the compiler places reaches further back than a
-// column); one barrier per slice.
+// units of the next slice (this tile's cs+1, or the block's next tile's first), two per tap
+// column right after that column's weight loads, and stores them into the other buffer one
+// column later, when they have long arrived (loads retire in order, so no wait the
+// compiler places reaches further back than a column); one barrier per slice.  The last
+// tap column also loads the next slice's first weight column.  One block per CU runs every
+// G-th tile (G = the grid); without ASYNC, one block per tile.
 template <typename T, int CIN, int COUT, int ROWS, int WAVES, int EPI, typename TO, bool ASYNC>
 __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restrict__ in, const T *__restrict__ wp,
                                                               const float *__restrict__ bias, int bias_pp, int relu,
