@@ -476,10 +476,10 @@ def main():
     if not args.no_serve:
         from paper_1701_03891_amd import serve
         qps = [float(q) for q in args.serve_qps.split(",") if q]
-        sv = serve.sweep_serving(qps, n_req=args.serve_requests, slots=2, budget_gib=16.0, warmup=1000,
+        sv = serve.sweep_serving(qps, n_req=args.serve_requests, slots=4, budget_gib=16.0, warmup=1000,
                                  at_fraction=0.7, log=lambda m: print(m, file=sys.stderr, flush=True))
         sv["workload"] = ("Poisson arrivals, 1-32 images per request, 9 networks "
-                          "(32/64/128 px x M/N 0.10/0.25/0.50), BF16, 2 streams, HIP graphs; "
+                          "(32/64/128 px x M/N 0.10/0.25/0.50), BF16, 4 streams, HIP graphs; "
                           f"{args.serve_requests} measured requests per load after 1000 warm-up")
         out["serving"] = sv
     print(json.dumps(out))

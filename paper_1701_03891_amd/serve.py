@@ -289,7 +289,7 @@ class GraphExecutor(Executor):
     """libdsi on one GPU: per slot a stream and a context; per (net, bucket, slot) a
     captured graph over static staging buffers."""
 
-    def __init__(self, nets, n_slots=2, buckets=DEFAULT_BUCKETS, device=0):
+    def __init__(self, nets, n_slots=4, buckets=DEFAULT_BUCKETS, device=0):
         import torch
 
         import paper_1701_03891_amd as P
@@ -413,14 +413,14 @@ def make_requests(nets, phis, n_req, qps, max_images=32, cfg_id=7, device="cuda:
     return reqs
 
 
-def run_serving(n_req=2000, qps=2000.0, slots=2, budget_gib=16.0, buckets=DEFAULT_BUCKETS, warmup=200,
+def run_serving(n_req=2000, qps=2000.0, slots=4, budget_gib=16.0, buckets=DEFAULT_BUCKETS, warmup=200,
                 sizes=(32, 64, 128), ratios=(0.10, 0.25, 0.50)):
     """One load point: `warmup` unmeasured requests, then n_req measured ones at `qps`."""
     return sweep_serving((qps,), n_req, slots, budget_gib, buckets, warmup, sizes, ratios,
                          at_fraction=None)["points"][0]
 
 
-def sweep_serving(qps_list, n_req=10000, slots=2, budget_gib=16.0, buckets=DEFAULT_BUCKETS, warmup=1000,
+def sweep_serving(qps_list, n_req=10000, slots=4, budget_gib=16.0, buckets=DEFAULT_BUCKETS, warmup=1000,
                   sizes=(32, 64, 128), ratios=(0.10, 0.25, 0.50), at_fraction=0.7, log=None):
     """Latency and throughput over offered loads.  Saturation is the delivered image
     rate at the highest offered load (offered above capacity, the server delivers its
@@ -462,7 +462,7 @@ if __name__ == "__main__":
     ap = argparse.ArgumentParser(description="continuous-batching recovery server benchmark")
     ap.add_argument("--requests", type=int, default=3000)
     ap.add_argument("--qps", type=float, default=2000.0)
-    ap.add_argument("--slots", type=int, default=2)
+    ap.add_argument("--slots", type=int, default=4)
     ap.add_argument("--budget-gib", type=float, default=16.0)
     a = ap.parse_args()
     print(json.dumps(run_serving(a.requests, a.qps, a.slots, a.budget_gib)))

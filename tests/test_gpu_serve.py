@@ -1,13 +1,14 @@
 """Serving loop on the GPU: graph-replayed batches of mixed networks overlap on
-two streams, and every request's result is bit-identical to recovering that
-request alone (per-image results do not depend on the batch they run in)."""
+two or four streams, and every request's result is bit-identical to recovering
+that request alone (per-image results do not depend on the batch they run in)."""
 import numpy as np
 import pytest
 
 pytestmark = pytest.mark.gpu
 
 
-def test_served_results_equal_results_alone():
+@pytest.mark.parametrize("slots", [2, 4])
+def test_served_results_equal_results_alone(slots):
     import torch
 
     import paper_1701_03891_amd as P
@@ -16,14 +17,14 @@ def test_served_results_equal_results_alone():
         pytest.skip("no GPU")
     nets, phis = serve.make_workload(sizes=(32, 64), ratios=(0.10, 0.25))
     buckets = (1, 2, 4, 8, 16, 32, 64)
-    ex = serve.GraphExecutor(nets, n_slots=2, buckets=buckets)
+    ex = serve.GraphExecutor(nets, n_slots=slots, buckets=buckets)
     reqs = serve.make_requests(nets, phis, 300, qps=20000.0, max_images=24)
     srv = serve.Server(ex, len(nets), buckets, budget=8 << 30)
     stats = srv.run(reqs)
     torch.cuda.synchronize()
     print("serving:", stats)
     assert all(r.finish is not None for r in reqs)
-    assert stats["max_concurrent_batches"] == 2
+    assert stats["max_concurrent_batches"] >= 2
     assert stats["mean_batch"] > 1.5        # requests were merged
     ctx = P.Context(0)
     alone = [ctx.prepare(*shape, params, prec=prec) for shape, params, prec in nets]
