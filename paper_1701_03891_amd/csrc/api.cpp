@@ -510,6 +510,12 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
 // even rounds of 506 blocks on 256 CUs; the single-channel ones have 1-2 pairs
 int wgrad_chunks(int B) { return std::max(1, std::min(B, 23)); }
 int wgrad_thin_chunks(int B) { return std::max(1, std::min(B, 128)); }
+// strip ranges of the channel-major conv2 kernel (6 blocks each, one block per CU):
+// 42 ranges fill 252 of the 256 CUs in one round
+int wgrad_vg_chunks(int B, int H, int W) {
+  const long strips = (long)B * ((H + 7) / 8) * ((W + 63) / 64);
+  return (int)std::max(1L, std::min(strips, 42L));
+}
 
 // Backward of the paper's network on the MFMA kernels.  gz3 = dL/dz3 fp32 [B][N].
 // Scratch: g2 (T, [B][2][N][16]), g1 (T, [B][4][N][16]), gxt fp32 [B][N], wgrad partials.
@@ -544,7 +550,7 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
     if (planar) {
       HIPCHK(dsi::to_planar((const bf16 *)g2, g2p, B, 32, N, s));
       HIPCHK(dsi::to_planar((const bf16 *)a1, a1p, B, 64, N, s));
-      HIPCHK(dsi::conv_wgrad_mid(g2p, a1p, 64, partial, nch, g->w[1], B, H, W, s, true));
+      HIPCHK(dsi::conv_wgrad_mid(g2p, a1p, 64, partial, wgrad_vg_chunks(B, H, W), g->w[1], B, H, W, s, true));
     } else {
       HIPCHK(dsi::conv_wgrad_mid((const bf16 *)g2, (const bf16 *)a1, 64, partial, nch, g->w[1], B, H, W, s));
     }
@@ -576,7 +582,7 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
 
 size_t backward_paper_scratch(const dsi_net &n, int B) {
   const size_t N = n.N, es = n.es;
-  const int nch = wgrad_chunks(B), ncht = wgrad_thin_chunks(B);
+  const int nch = std::max(wgrad_chunks(B), wgrad_vg_chunks(B, n.d.n1, n.d.n2)), ncht = wgrad_thin_chunks(B);
   size_t part = std::max({dsi::conv_wgrad_mid_partial_floats(64, nch), dsi::conv_wgrad_thin_partial_floats(64, ncht),
                           dsi::conv_wgrad_thin_partial_floats(32, ncht)});
   const size_t planar = (n.prec == DSI_BF16 && n.d.n2 % 8 == 0) ? rnd(B * 32 * N * 2) + rnd(B * 64 * N * 2) : 0;

@@ -3,6 +3,7 @@
 
 #include <hip/hip_runtime.h>
 #include <stdint.h>
+#include <utility>
 
 typedef __bf16 bf16;
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
@@ -59,6 +60,13 @@ DSI_INLINE float e4m3_to_f32(u8 c) {
   float v = e == 0 ? ldexpf((float)m, -9) : ldexpf((float)(8u + m), (int)e - 10);
   return s ? -v : v;
 }
+
+// f(std::integral_constant<int, I>{}) for I = 0 .. N-1, in order: a loop whose index
+// is a compile-time constant in the body (fully unrolled straight-line code)
+template <typename F, int... I> DSI_INLINE void static_for_seq(F &&f, std::integer_sequence<int, I...>) {
+  (f(std::integral_constant<int, I>{}), ...);
+}
+template <int N, typename F> DSI_INLINE void static_for(F &&f) { static_for_seq(f, std::make_integer_sequence<int, N>{}); }
 
 // ------------------------------------------------------------------ XCDs
 // The workgroups of a launch go to the 8 XCDs in turn (block i to XCD i % 8), and each

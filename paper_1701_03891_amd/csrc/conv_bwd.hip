@@ -15,7 +15,10 @@
 // Accumulators (11 u x 32 x 32) live across all strips and images of the
 // block; each block then sums its four waves' accumulators in wave order and
 // writes them, and a second kernel sums the blocks' partials in a fixed order
-// (deterministic).
+// (deterministic).  That blocked kernel serves widths W % 8 != 0; otherwise the
+// activations and gradients are first copied channel-major and
+// conv_wgrad_mid_vg_kernel (below) lets the four waves of a block share one staged
+// strip across four tap columns.
 #include "common.h"
 #include "internal.h"
 
@@ -201,67 +204,149 @@ hipError_t to_planar(const bf16 *in, bf16 *out, int B, int C, int HW, hipStream_
   return hipGetLastError();
 }
 
-// 8 consecutive bf16 starting S elements into the 16 of (lo, hi)
-template <int S> DSI_INLINE i32x4 window8(const i32x4 &lo, const i32x4 &hi) {
-  const unsigned d[8] = {(unsigned)lo[0], (unsigned)lo[1], (unsigned)lo[2], (unsigned)lo[3],
-                         (unsigned)hi[0], (unsigned)hi[1], (unsigned)hi[2], (unsigned)hi[3]};
-  i32x4 r;
-#pragma unroll
-  for (int i = 0; i < 4; ++i)
-    r[i] = (S & 1) ? (int)__builtin_amdgcn_alignbit(d[i + S / 2 + 1], d[i + S / 2], 16) : (int)d[i + S / 2];
-  return r;
+// buffer_load_dwordx4 ... lds: the LLVM intrinsic, declared by its name so that the
+// host pass of the compiler sees an ordinary declaration.  rsrc is a raw buffer
+// resource (base, byte size); each lane's 16 bytes at byte offset voffset go to LDS
+// at dst + 16 * lane (dst: the wave's common LDS address), zeros when the offset lies
+// outside the resource.
+__device__ void llvm_buffer_load_lds(i32x4 rsrc, __attribute__((address_space(3))) void *lds, int size, int voffset,
+                                     int soffset, int offset, int aux) __asm("llvm.amdgcn.raw.buffer.load.lds");
+DSI_INLINE i32x4 buffer_rsrc(const void *base, int bytes) {
+  const unsigned long p = reinterpret_cast<unsigned long>(base);
+  // (word 3: the raw-buffer configuration of gfx9 parts)
+  return i32x4{(int)(unsigned)p, (int)((unsigned)(p >> 32) & 0xffffu), bytes, 0x00020000};
 }
-DSI_INLINE i32x4 window8(const i32x4 &lo, const i32x4 &hi, int s) {
-  switch (s) {  // s is uniform across the block
-    case 0: return window8<0>(lo, hi);
-    case 1: return window8<1>(lo, hi);
-    case 2: return window8<2>(lo, hi);
-    case 3: return window8<3>(lo, hi);
-    case 4: return window8<4>(lo, hi);
-    case 5: return window8<5>(lo, hi);
-    case 6: return window8<6>(lo, hi);
-    default: return window8<7>(lo, hi);
-  }
+DSI_INLINE void buffer_load_lds16(const i32x4 &rsrc, i32x4 *dst, int voffset) {
+  llvm_buffer_load_lds(rsrc, (__attribute__((address_space(3))) void *)dst, 16, voffset, 0, 0, 0);
 }
 
-// Source of the zero units that halo positions outside the image load through the
-// direct-to-LDS loads (those take a global address in every lane).
-__device__ __attribute__((aligned(16))) unsigned int wg_zero_unit[4] = {0u, 0u, 0u, 0u};
+// conv2 weight gradient by tap-column groups, from channel-major g [B][32][H][W] and
+// a [B][CIN][H][W] (W % 8 == 0, CIN * H * W < 2^31, B * H * W < 2^31).  A block owns a
+// 32-channel input tile ct, a group of four tap columns and a range of strips (8
+// output rows x 64 activation columns, in (image, row strip, column strip) order).
+// Its wave w computes tap column v = 4 vg + w over every column of the strip (the
+// twelfth slot repeats v = 10 and stores nothing), so four tap columns share one
+// staged strip:
+//   dW[co][ci][u][v] = sum_{i,j'} G[co][i][j' - v + 5] A[ci][i + u - 5][j'].
+// A strip sits in LDS as two 32-column halves: activations (18 rows: 16 in the main
+// tile, 2 in a tail) and gradients (8 rows x 64 columns, j0 - 16 .. j0 + 47 around the
+// half starting at j0).  Every byte arrives by direct-to-LDS loads
+// (buffer_load_dwordx4 ... lds; one instruction moves one channel's 16 x 32 activations
+// or 8 x 64 gradients), 18 per wave per half, one per walk step: while the waves compute
+// on one half, the other half of the next strip is loaded, so a barrier (two per strip)
+// waits only for loads issued at least 18 steps earlier.  The walk is 4 chunks x 18
+// input rows; each step's activation fragment is read 6 steps ahead and feeds up to 8
+// MFMAs (one per filter row u).  The gradient fragment of row i starts 21 - v elements
+// into its window row, a 16-byte LDS read at a 2-byte boundary.  Positions outside the
+// image read past the buffer resource, which yields zeros.  Each wave stores its tap column's partial sums;
+// conv_wgrad_mid_reduce_kernel adds the chunks in a fixed order.
+constexpr int WV_CS = 65;        // channel stride (16-byte units) of the main and gradient tiles
+constexpr int WV_TS = 9;         // channel stride of the activation tail (rows 16 and 17)
+constexpr int WV_TN = 8 * 64;    // tail capacity: eight load instructions
+constexpr int WV_LA = 8;         // read-ahead of the activation fragments (steps)
 
-// conv2 weight gradient from channel-major g [B][32][H][W] and a [B][CIN][H][W]
-// (W % 8 == 0, CIN * H * W < 2^31).  Same blocks and MFMA walk as
-// conv_wgrad_mid_kernel, but a strip covers 64 ACTIVATION columns j' = j0 .. j0+63 and
-// the gradient is the shifted operand:
-//   dW[co][ci][u][v] = sum_{i,j'} G[co][i][j' - v + 5] A[ci][i + u - 5][j'],
-// which counts every (i, j) once over the strips.  Per strip a wave first reads every
-// fragment of its walk into registers; then, while its MFMAs run, it issues the next
-// strip's loads between them: the activation strip (aligned) with direct-to-LDS loads
-// (global_load_lds_dwordx4), the gradient strip (8 rows, shifted by 5 - v) into
-// registers as two aligned vectors per unit, funnel-shifted and stored after the walk.
-// No LDS read follows the direct-to-LDS loads until the next strip (the compiler makes
-// every LDS read wait for them).  Positions outside the image load a zero unit, so no
-// load sits behind a branch, and the last strip re-loads itself (harmless) for the same
-// reason.
 template <int CIN>
-__global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *__restrict__ g,
-                                                                    const bf16 *__restrict__ a,
-                                                                    float *__restrict__ partial, int B, int H, int W,
-                                                                    int nchunk) {
-  // LDS tiles [channel][row][64 cols], each channel's tile padded to 16 bytes past a
-  // multiple of 256: the 32 lanes of a half-wave read 32 channels of the same (row,
-  // col), which then fall on distinct banks
-  constexpr int GS = WG_SR * WG_TW + 8, AS = WG_LR * WG_TW + 8;   // channel strides (elements)
-  __shared__ __attribute__((aligned(16))) bf16 gl[32 * GS];
-  __shared__ __attribute__((aligned(16))) bf16 al[32 * AS];
+__global__ __launch_bounds__(256) void conv_wgrad_mid_vg_kernel(const bf16 *__restrict__ g,
+                                                                const bf16 *__restrict__ a,
+                                                                float *__restrict__ partial, int B, int H, int W,
+                                                                int nchunk) {
+  // channel strides of 1040 and 144 bytes: the 32 lanes of a half-wave read 32 channels
+  // of one (row, column), on distinct banks
+  __shared__ __attribute__((aligned(16))) i32x4 am0[32 * WV_CS], am1[32 * WV_CS], at0[WV_TN], at1[WV_TN];
+  __shared__ __attribute__((aligned(16))) i32x4 gg0[32 * WV_CS], gg1[32 * WV_CS];
   const int tid = threadIdx.x, lane = tid & 63, h = lane >> 5, c32 = lane & 31;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
-  // the (CIN/32) * 11 blocks of one image chunk read the same data: neighbours on one XCD
-  const int L = xcd_logical(blockIdx.x, gridDim.x), ncombo = (CIN / 32) * 11;
-  const int chunk = L / ncombo, v = (L % ncombo) % 11, ct = (L % ncombo) / 11;
-  const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
-  const int sg = (13 - v) & 7;   // (5 - v) mod 8: offset of the G window in its aligned vectors
-  const bf16 *zero = reinterpret_cast<const bf16 *>(wg_zero_unit);
-  const int urow = lane >> 3, ucol = 8 * (lane & 7);   // a lane's unit in an 8-row x 64-column part
+  constexpr int NCOMBO = (CIN / 32) * 3;
+  // the NCOMBO blocks of one strip range read the same strips: neighbours on one XCD
+  const int L = xcd_logical(blockIdx.x, gridDim.x);
+  const int chunk = L / NCOMBO, combo = L % NCOMBO, ct = combo / 3, vg = combo % 3;
+  const int vw = 4 * vg + wave, v = vw < 11 ? vw : 10;
+  const int nrs = (H + 7) / 8, ncs = (W + 63) / 64;
+  const int S = B * nrs * ncs;
+  const int s0 = (int)((long)S * chunk / nchunk), s1 = (int)((long)S * (chunk + 1) / nchunk);
+  const int HW = H * W;
+  const bf16 *aimg0 = a + (long)ct * 32 * HW;
+
+  // a lane's unit in each kind of load instruction (fixed for the kernel):
+  //   main: row lane / 4 of 16, unit lane % 4; gradient: row lane / 8, unit lane % 8;
+  //   tail instruction 2 wave + q: unit t = 64 (2 wave + q) + lane of [channel][9]
+  const int rowA = lane >> 2, colA = 8 * (lane & 3), rowG = lane >> 3, colG = 8 * (lane & 7) - 16;
+  int cT[2], rowT[2], colT[2];
+  bool okT[2];
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const int t = 64 * (2 * wave + q) + lane, c = t / WV_TS, slot = t - c * WV_TS;
+    okT[q] = c < 32 && slot < 8;
+    cT[q] = okT[q] ? c : 0;
+    rowT[q] = 16 + (slot >> 2);
+    colT[q] = 8 * (slot & 3);
+  }
+  struct Strip { int b, i0, j0; };
+  auto strip_at = [&](int s) {
+    const int b = s / (nrs * ncs), rem = s - b * nrs * ncs, rs = rem / ncs;
+    return Strip{b, rs * 8, (rem - rs * ncs) * 64};
+  };
+  // Buffer resources over one channel plane (main and gradient tiles) or the 32
+  // channels (tail) of the strip's image, in bytes; a load at offset 2^31 lies outside
+  // and writes zeros, which is how halo positions outside the image are filled.
+  constexpr int OOB = (int)0x80000000u;
+  auto rsrc = [&](const bf16 *base, int bytes) { return buffer_rsrc(base, bytes); };
+  // per-lane byte offsets of the load jobs of half hs of strip sp (the same for every
+  // channel of the main and gradient tiles)
+  // (and the strip's first channel planes of this wave's jobs)
+  struct Offs { int a, t0, t1, g; const bf16 *pa, *pt, *pg; };
+  auto offsets = [&](const Strip &sp, int hs) {
+    const int jh = sp.j0 + 32 * hs;
+    Offs o;
+    o.pt = aimg0 + (long)sp.b * CIN * HW;
+    o.pa = o.pt + (long)(8 * wave) * HW;
+    o.pg = g + ((long)sp.b * 32 + 8 * wave) * HW;
+    {
+      const int gi = sp.i0 - 5 + rowA, gj = jh + colA;
+      o.a = ((gi >= 0) & (gi < H) & (gj < W)) ? 2 * (gi * W + gj) : OOB;
+    }
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+      const int gi = sp.i0 - 5 + rowT[q], gj = jh + colT[q];
+      const int t = (okT[q] & (gi >= 0) & (gi < H) & (gj < W)) ? 2 * (cT[q] * HW + gi * W + gj) : OOB;
+      if (q == 0) o.t0 = t; else o.t1 = t;
+    }
+    {
+      const int gi = sp.i0 + rowG, gj = jh + colG;
+      o.g = ((gi < H) & (gj >= 0) & (gj < W)) ? 2 * (gi * W + gj) : OOB;
+    }
+    return o;
+  };
+  // load job m (0..17) of a half (offsets o): 0..7 the activation main tile of
+  // channels 8 wave .. 8 wave + 7, 8..9 the tail, 10..17 the gradient tile of the same
+  // channels
+  auto dma_job = [&](const Offs &o, int hs, int m) {
+    if (m < 8)
+      buffer_load_lds16(rsrc(o.pa + m * HW, 2 * HW), (hs ? am1 : am0) + (8 * wave + m) * WV_CS, o.a);
+    else if (m < 10)
+      buffer_load_lds16(rsrc(o.pt, 64 * HW), (hs ? at1 : at0) + 64 * (2 * wave + m - 8), m == 8 ? o.t0 : o.t1);
+    else
+      buffer_load_lds16(rsrc(o.pg + (m - 10) * HW, 2 * HW), (hs ? gg1 : gg0) + (8 * wave + m - 10) * WV_CS, o.g);
+  };
+  // fragments of chunk k (columns 16k .. 16k + 15 of the strip): activation row r and
+  // gradient row i
+  auto read_a = [&](int k, int r) {
+    Frag8<bf16> f;
+    const i32x4 x = r < 16 ? ((k < 2) ? am0 : am1)[c32 * WV_CS + r * 4 + 2 * (k & 1) + h]
+                           : ((k < 2) ? at0 : at1)[c32 * WV_TS + (r - 16) * 4 + 2 * (k & 1) + h];
+    __builtin_memcpy(&f.v, &x, 16);
+    return f;
+  };
+  // (the gradient fragment of row i in chunk k starts 16 (k % 2) + 8h + 21 - v elements
+  // into its window row: one 16-byte read at a 2-byte boundary, which measured faster
+  // than two aligned reads shifted in registers)
+  const int goff = 8 * h + 21 - v;
+  auto read_g = [&](int k, int i) {
+    const bf16 *p = reinterpret_cast<const bf16 *>((k < 2) ? gg0 : gg1) + c32 * WV_CS * 8 + i * 64 + 16 * (k & 1) + goff;
+    Frag8<bf16> f;
+    f.v = *reinterpret_cast<const bf16x8 *>(p);
+    return f;
+  };
 
   f32x16 acc[11];
 #pragma unroll
@@ -269,95 +354,66 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_planar_kernel(const bf16 *
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[u][r] = 0.0f;
 
-  // A strip rows i0-5 .. i0+12 of channel c as three parts of 8 rows (the third: 2 rows,
-  // lanes 0..15); wave w issues the 24 (channel, part) loads of channels 8w .. 8w+7
-  auto a_dma = [&](int t, const bf16 *aimg, int i0, int j0) {
-    const int c = 8 * wave + t / 3, part = t % 3;
-    if (part == 2 && lane >= 16) return;
-    const int gi = i0 - 5 + 8 * part + urow, gj = j0 + ucol;
-    const bool in = gi >= 0 && gi < H && gj < W;
-    const bf16 *src = in ? aimg + (c * H + gi) * W + gj : zero;
-    __builtin_amdgcn_global_load_lds(src, (__attribute__((address_space(3))) void *)(al + c * AS + part * 64 * 8), 16,
-                                     0, 0);
-  };
-  // G strip unit (channel wave + 4 it, row urow, column group) from two aligned vectors
-  auto g_load = [&](int it, const bf16 *gimg, int i0, int j0, i32x4 &lo, i32x4 &hi) {
-    const int c = wave + 4 * it, gi = i0 + urow, base = j0 - v + 5 + ucol - sg;   // aligned
-    const bf16 *row = gimg + (c * H + gi) * W;
-    const bool rin = gi < H;
-    lo = *reinterpret_cast<const i32x4 *>(rin && base >= 0 && base < W ? row + base : zero);
-    hi = *reinterpret_cast<const i32x4 *>(rin && base + 8 >= 0 && base + 8 < W ? row + base + 8 : zero);
-  };
-  constexpr int IG = 32 * WG_SR * 8 / 256;   // G units per thread
-  auto g_store = [&](int it, const i32x4 &lo, const i32x4 &hi) {
-    const int c = wave + 4 * it;
-    *reinterpret_cast<i32x4 *>(gl + c * GS + urow * WG_TW + ucol) = window8(lo, hi, sg);
-  };
-
-  // strips in order (image, row strip, column strip); (nb, ni, nj) is the next one staged
-  const int nstrip = (b1 - b0) * ((H + WG_SR - 1) / WG_SR) * ((W + WG_TW - 1) / WG_TW);
-  int nb = b0, ni = 0, nj = 0;
-  auto advance = [&]() {
-    nj += WG_TW;
-    if (nj >= W) {
-      nj = 0;
-      ni += WG_SR;
-      if (ni >= H) {
-        ni = 0;
-        ++nb;
-      }
-    }
-  };
-  if (nstrip > 0) {
-    const bf16 *aimg = a + ((long)nb * CIN + ct * 32) * H * W, *gimg = g + (long)nb * 32 * H * W;
+  constexpr int NST = 4 * 18, LA = WV_LA, B1 = 35 - LA, B2 = 71 - LA;
+  static_assert(NST % LA == 0, "the read-ahead ring wraps with the strip");
+  static_assert(18 - LA <= B1 + 1 && B1 + 18 <= B2, "load windows overlap");
+  Frag8<bf16> aq[LA], gq[8];
+  if (s0 < s1) {
+    const Strip sp = strip_at(s0);
+    const Offs o0 = offsets(sp, 0), o1 = offsets(sp, 1);
 #pragma unroll
-    for (int t = 0; t < 24; ++t) a_dma(t, aimg, ni, nj);
-    i32x4 lo[IG], hi[IG];
+    for (int m = 0; m < 18; ++m) dma_job(o0, 0, m);
 #pragma unroll
-    for (int it = 0; it < IG; ++it) g_load(it, gimg, ni, nj, lo[it], hi[it]);
-#pragma unroll
-    for (int it = 0; it < IG; ++it) g_store(it, lo[it], hi[it]);
-    advance();
-  }
-  for (int q = 0; q < nstrip; ++q) {
-    __builtin_amdgcn_s_waitcnt(0);   // this strip's direct-to-LDS loads have landed
+    for (int m = 0; m < WV_LA; ++m) dma_job(o1, 1, m);   // (the rest at the walk's first steps)
+    __builtin_amdgcn_s_waitcnt(0);   // (a barrier alone does not wait for these loads)
     __syncthreads();
-    // every fragment of the walk into registers
-    Frag8<bf16> gf[WG_SR], af[WG_LR];
 #pragma unroll
-    for (int i = 0; i < WG_SR; ++i)
-      gf[i].v = *reinterpret_cast<const bf16x8 *>(gl + c32 * GS + i * WG_TW + 16 * wave + 8 * h);
-#pragma unroll
-    for (int r = 0; r < WG_LR; ++r)
-      af[r].v = *reinterpret_cast<const bf16x8 *>(al + c32 * AS + r * WG_TW + 16 * wave + 8 * h);
-    __syncthreads();                 // the LDS tiles are free
-    const int sb = nb < b1 ? nb : b1 - 1;   // after the last strip: a valid strip, loaded again
-    const bf16 *aimg = a + ((long)sb * CIN + ct * 32) * H * W, *gimg = g + (long)sb * 32 * H * W;
-    i32x4 lo[IG], hi[IG];
-    // the walk, with the next strip's loads spread between its MFMAs (the gradient's
-    // first, so the stores after the walk wait for them alone)
-#pragma unroll
-    for (int r = 0; r < WG_LR; ++r) {
+    for (int q = 0; q < LA; ++q) {
+      aq[q] = read_a(0, q);
+      if (q < 8) gq[q] = read_g(0, q);
+    }
+  }
+  for (int s = s0; s < s1; ++s) {
+    // (the last strip loads itself again: the same bytes into buffers nothing reads)
+    const Strip cur = strip_at(s), nxt = strip_at(s + 1 < s1 ? s + 1 : s);
+    const Offs oc1 = offsets(cur, 1), on0 = offsets(nxt, 0), on1 = offsets(nxt, 1);
+    static_for<NST>([&](auto stc) {
+      constexpr int st = decltype(stc)::value, k = st / 18, r = st % 18;
+      const Frag8<bf16> x = aq[st % LA];
 #pragma unroll
       for (int u = 0; u < 11; ++u) {
         const int i = r - u;
-        if (i >= 0 && i < WG_SR) gf[i].mma(af[r], acc[u]);
+        if (i >= 0 && i < 8) gq[i].mma(x, acc[u]);
       }
-      if (r < IG) g_load(r, gimg, ni, nj, lo[r], hi[r]);
-      if (r >= 2 && r < 14) {
-        a_dma(2 * (r - 2), aimg, ni, nj);
-        a_dma(2 * (r - 2) + 1, aimg, ni, nj);
+      {   // reads for step st + LA (past the end: the next strip's first steps)
+        constexpr int n = (st + LA) % NST, nk = n / 18, nr = n % 18;
+        aq[st % LA] = read_a(nk, nr);
+        if constexpr (nr < 8) gq[nr] = read_g(nk, nr);
+      }
+      // one load a step: this strip's second half (jobs LA..17), the next strip's first
+      // half after the first barrier and its second half (jobs 0..LA-1) after the second
+      if constexpr (st < 18 - LA) dma_job(oc1, 1, st + LA);
+      else if constexpr (st > B1 && st <= B1 + 18) dma_job(on0, 0, st - B1 - 1);
+      else if constexpr (st > B2) dma_job(on1, 1, st - B2 - 1);
+      // after step B1 every read of the first half has been issued (the last, for step
+      // 35, in this step), after step B2 every read of the second half; the reads issued
+      // after a barrier find the half it waited for
+      if constexpr (st == B1 || st == B2) {
+        __builtin_amdgcn_s_waitcnt(0);
+        __syncthreads();
       }
       __builtin_amdgcn_sched_barrier(0);
-    }
-#pragma unroll
-    for (int it = 0; it < IG; ++it) g_store(it, lo[it], hi[it]);
-    advance();
+    });
   }
-  __builtin_amdgcn_s_waitcnt(0);     // the last strip's repeated loads have landed
-  __syncthreads();
-  store_block_partial<false>(acc, reinterpret_cast<float *>(al),
-                             partial + ((long)(ct * 11 + v) * nchunk + chunk) * 11 * 1024);
+  if (vw < 11) {
+    float *dst = partial + ((long)(ct * 11 + v) * nchunk + chunk) * 11 * 1024;
+#pragma unroll
+    for (int u = 0; u < 11; ++u)
+#pragma unroll
+      for (int r4 = 0; r4 < 4; ++r4)
+        *reinterpret_cast<f32x4 *>(dst + ((u * 4 + r4) * 64 + lane) * 4) =
+            f32x4{acc[u][4 * r4], acc[u][4 * r4 + 1], acc[u][4 * r4 + 2], acc[u][4 * r4 + 3]};
+  }
 }
 
 // Partial-sum reduction: a block owns RED_SLOTS consecutive accumulator slots; its
@@ -400,12 +456,15 @@ __global__ __launch_bounds__(256) void conv_wgrad_mid_reduce_kernel(const float 
 
 size_t conv_wgrad_mid_partial_floats(int CIN, int nchunk) { return (size_t)(CIN / 32) * 11 * nchunk * 11 * 1024; }
 
+// nchunk: image chunks of the blocked kernel, strip ranges of the channel-major one (the
+// partials are [(ct * 11 + v) * nchunk + chunk][11 u][1024] either way)
 hipError_t conv_wgrad_mid(const bf16 *g, const bf16 *a, int CIN, float *partial, int nchunk, float *dw, int B,
                           int H, int W, hipStream_t s, bool planar) {
   const int blocks = (CIN / 32) * 11 * nchunk;
-  if (planar && (W % 8 != 0 || (long)CIN * H * W >= (1L << 31))) return hipErrorInvalidValue;
+  if (planar && (W % 8 != 0 || (long)CIN * H * W >= (1L << 31) || (long)B * H * W >= (1L << 31)))
+    return hipErrorInvalidValue;
   if (CIN == 64 && planar)
-    conv_wgrad_mid_planar_kernel<64><<<blocks, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
+    conv_wgrad_mid_vg_kernel<64><<<(CIN / 32) * 3 * nchunk, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
   else if (CIN == 64)
     conv_wgrad_mid_kernel<64><<<blocks, 256, 0, s>>>(g, a, partial, B, H, W, nchunk);
   else if (CIN == 32 && !planar)
