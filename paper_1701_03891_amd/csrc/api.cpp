@@ -509,7 +509,12 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
 // the conv2 kernel has 22 such pairs and one block per CU fits, so 23 chunks make two
 // even rounds of 506 blocks on 256 CUs; the single-channel ones have 1-2 pairs
 int wgrad_chunks(int B) { return std::max(1, std::min(B, 23)); }
-int wgrad_thin_chunks(int B) { return std::max(1, std::min(B, 128)); }
+// strip ranges of the single-channel-side kernels (8 x 64 strips): 256 per 32-channel
+// tile, one block per CU for layer 3's 32 channels, two for layer 1's 64
+int wgrad_thin_chunks(int B, int H, int W) {
+  const long strips = (long)B * ((H + 7) / 8) * ((W + 63) / 64);
+  return (int)std::max(1L, std::min(strips, 256L));
+}
 // strip ranges of the channel-major conv2 kernel (6 blocks each, one block per CU):
 // 42 ranges fill 252 of the 256 CUs in one round
 int wgrad_vg_chunks(int B, int H, int W) {
@@ -535,7 +540,7 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
   bf16 *g2p = at<bf16>(scratch, off); off += planar ? rnd((size_t)B * 32 * N * 2) : 0;
   bf16 *a1p = at<bf16>(scratch, off); off += planar ? rnd((size_t)B * 64 * N * 2) : 0;
   float *partial = at<float>(scratch, off);
-  const int nch = wgrad_chunks(B), ncht = wgrad_thin_chunks(B);
+  const int nch = wgrad_chunks(B), ncht = wgrad_thin_chunks(B, H, W);
   const ActView v1{1, H, W, 0}, v32{32, H, W, 1}, v64{64, H, W, 1};
   // layer 3: dW3, db3, then g2 = (a2 > 0) * dgrad(gz3)
   if constexpr (bf) {
@@ -582,7 +587,7 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
 
 size_t backward_paper_scratch(const dsi_net &n, int B) {
   const size_t N = n.N, es = n.es;
-  const int nch = std::max(wgrad_chunks(B), wgrad_vg_chunks(B, n.d.n1, n.d.n2)), ncht = wgrad_thin_chunks(B);
+  const int nch = std::max(wgrad_chunks(B), wgrad_vg_chunks(B, n.d.n1, n.d.n2)), ncht = wgrad_thin_chunks(B, n.d.n1, n.d.n2);
   size_t part = std::max({dsi::conv_wgrad_mid_partial_floats(64, nch), dsi::conv_wgrad_thin_partial_floats(64, ncht),
                           dsi::conv_wgrad_thin_partial_floats(32, ncht)});
   const size_t planar = (n.prec == DSI_BF16 && n.d.n2 % 8 == 0) ? rnd(B * 32 * N * 2) + rnd(B * 64 * N * 2) : 0;

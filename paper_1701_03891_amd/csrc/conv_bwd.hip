@@ -498,7 +498,7 @@ constexpr int TG_PITCH = WG_TW + 16;  // thin tile pitch: cols -5 .. 74 (+ paddi
 // wide [B][CW/16][H][W][16] (bf16); thin [B][H][W] (TT, converted to bf16)
 // partial [ct*nchunk + chunk][11 u][352] fp32 (store_block_partial)
 template <int MODE, typename TT>
-__global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__restrict__ wide, const TT *__restrict__ thin,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(MODE == THIN_OUT ? 1 : 2))) void conv_wgrad_thin_kernel(const bf16 *__restrict__ wide, const TT *__restrict__ thin,
                                                               int CW, float *__restrict__ partial, int B, int H, int W,
                                                               int nchunk) {
   constexpr int WR = MODE == THIN_OUT ? WG_LR : WG_SR;   // wide rows per strip
@@ -519,7 +519,11 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
   };
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, h = lane >> 5, c32 = lane & 31;
   const int chunk = blockIdx.x % nchunk, ct = blockIdx.x / nchunk;
-  const int b0 = (int)((long)chunk * B / nchunk), b1 = (int)((long)(chunk + 1) * B / nchunk);  // balanced
+  // a block owns a balanced range of strips (8 rows x 64 columns, in (image, row
+  // strip, column strip) order)
+  const int nrs = (H + WG_SR - 1) / WG_SR, ncs = (W + WG_TW - 1) / WG_TW;
+  const int S = B * nrs * ncs;   // (B * H * W < 2^31)
+  const int s0 = (int)((long)S * chunk / nchunk), s1 = (int)((long)S * (chunk + 1) / nchunk);
   const int wrow0 = MODE == THIN_OUT ? -5 : 0, trow0 = MODE == THIN_OUT ? 0 : -5;
 
   f32x16 acc[11];
@@ -528,65 +532,80 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_kernel(const bf16 *__rest
 #pragma unroll
     for (int r = 0; r < 16; ++r) acc[u][r] = 0.0f;
 
-  for (int b = b0; b < b1; ++b)
-    for (int i0 = 0; i0 < H; i0 += WG_SR)
-      for (int j0 = 0; j0 < W; j0 += WG_TW) {
-        __syncthreads();
-        // wide strip (32 channels, transposed to planar) and thin strip; every load of a
-        // thread is issued before its LDS stores
-        constexpr int NWU = WR * WG_TW * 4, NTU = TR * TG_PITCH;
-        constexpr int IW = (NWU + 255) / 256, IT = (NTU + 255) / 256, BW = 8;
-#pragma unroll 1
-        for (int i0w = 0; i0w < IW; i0w += BW) {
-          i32x4 wv[BW];
+  // Staging.  The wide strip moves as 8 x 8 blocks (8 channels x 8 columns of one row):
+  // a thread loads the block's 8 pixels (16 bytes of 8 channels each), transposes them
+  // in registers and stores 8 rows of 8 columns as 16-byte LDS writes.  For layer 3
+  // both tiles of the next strip are loaded into registers while this strip's MFMAs
+  // run.
+  constexpr int NBLK = WR * (WG_TW / 8) * 4, NB = (NBLK + 255) / 256;
+  constexpr int NTU = TR * TG_PITCH, IT = (NTU + 255) / 256;
+  i32x4 wv[NB][8];
+  float tv[IT];
+  auto strip_load = [&](int sidx) {
+    const bool live = sidx < s1;
+    const int b = live ? sidx / (nrs * ncs) : 0, rem = sidx - b * nrs * ncs;
+    const int i0 = (rem / ncs) * WG_SR, j0 = (rem % ncs) * WG_TW;
 #pragma unroll
-          for (int j = 0; j < BW; ++j) {
-            const int idx = tid + (i0w + j) * 256;
-            const int q = idx & 3, pix = idx >> 2;
-            const int row = pix / WG_TW, col = pix - row * WG_TW;
-            const int gi = i0 + wrow0 + row, gj = j0 + col;
-            const int c0 = ct * 32 + q * 8;
-            wv[j] = i32x4{0, 0, 0, 0};
-            if (i0w + j < IW && idx < NWU && gi >= 0 && gi < H && gj < W)
-              wv[j] = *reinterpret_cast<const i32x4 *>(wide + ((((long)b * (CW / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15));
-          }
+    for (int n = 0; n < NB; ++n) {
+      const int blk = tid + n * 256, q = blk & 3, cg = (blk >> 2) & 7, row = blk >> 5;
+      const int gi = i0 + wrow0 + row, gj = j0 + 8 * cg, c0 = ct * 32 + q * 8;
+      const bool ok = live && blk < NBLK && gi >= 0 && gi < H;
+      const bf16 *src = wide + ((((long)b * (CW / 16) + (c0 >> 4)) * H + gi) * W + gj) * 16 + (c0 & 15);
 #pragma unroll
-          for (int j = 0; j < BW; ++j) {
-            const int idx = tid + (i0w + j) * 256;
-            const int q = idx & 3, pix = idx >> 2;
-            const int row = pix / WG_TW, col = pix - row * WG_TW;
-            if (i0w + j < IW && idx < NWU) {
-              bf16x8 e8;
-              __builtin_memcpy(&e8, &wv[j], 16);
+      for (int e = 0; e < 8; ++e) {
+        wv[n][e] = i32x4{0, 0, 0, 0};
+        if (ok && gj + e < W) wv[n][e] = *reinterpret_cast<const i32x4 *>(src + e * 16);
+      }
+    }
 #pragma unroll
-              for (int e = 0; e < 8; ++e) wl[((q * 8 + e) * WR + row) * WG_GW + col] = e8[e];
-            }
-          }
+    for (int it = 0; it < IT; ++it) {
+      const int idx = tid + it * 256;
+      const int row = idx / TG_PITCH, col = idx - row * TG_PITCH;
+      const int gi = i0 + trow0 + row, gj = j0 - 5 + col;
+      tv[it] = 0.0f;
+      if (live && idx < NTU && gi >= 0 && gi < H && gj >= 0 && gj < W && col < WG_TW + 10)
+        tv[it] = to_f32(thin[((long)b * H + gi) * W + gj]);
+    }
+  };
+  auto strip_store = [&]() {
+#pragma unroll
+    for (int n = 0; n < NB; ++n) {
+      const int blk = tid + n * 256, q = blk & 3, cg = (blk >> 2) & 7, row = blk >> 5;
+      if (blk < NBLK) {
+        // channel 8q + c of pixels 8cg .. 8cg + 7: dword k holds pixels 2k, 2k + 1
+#pragma unroll
+        for (int c = 0; c < 8; ++c) {
+          const unsigned sel = (c & 1) ? 0x07060302u : 0x05040100u;
+          i32x4 o;
+#pragma unroll
+          for (int k = 0; k < 4; ++k)
+            o[k] = (int)__builtin_amdgcn_perm((unsigned)wv[n][2 * k + 1][c >> 1], (unsigned)wv[n][2 * k][c >> 1], sel);
+          *reinterpret_cast<i32x4 *>(wl + ((q * 8 + c) * WR + row) * WG_GW + 8 * cg) = o;
         }
-        {
-          float tv[IT];
+      }
+    }
 #pragma unroll
-          for (int it = 0; it < IT; ++it) {
-            const int idx = tid + it * 256;
-            const int row = idx / TG_PITCH, col = idx - row * TG_PITCH;
-            const int gi = i0 + trow0 + row, gj = j0 - 5 + col;
-            tv[it] = 0.0f;
-            if (idx < NTU && gi >= 0 && gi < H && gj >= 0 && gj < W && col < WG_TW + 10)
-              tv[it] = to_f32(thin[((long)b * H + gi) * W + gj]);
-          }
-#pragma unroll
-          for (int it = 0; it < IT; ++it) {
-            const int idx = tid + it * 256;
-            if (idx < NTU) {
-              const bf16 e = (bf16)tv[it];
-              const int col = idx % TG_PITCH;
-              tl[idx] = e;
-              if (col > 0) tl[TCOPY + idx - 1] = e;
-              if (col == TG_PITCH - 1) tl[TCOPY + idx] = (bf16)0.0f;
-            }
-          }
-        }
+    for (int it = 0; it < IT; ++it) {
+      const int idx = tid + it * 256;
+      if (idx < NTU) {
+        const bf16 e = (bf16)tv[it];
+        const int col = idx % TG_PITCH;
+        tl[idx] = e;
+        if (col > 0) tl[TCOPY + idx - 1] = e;
+        if (col == TG_PITCH - 1) tl[TCOPY + idx] = (bf16)0.0f;
+      }
+    }
+  };
+  // (layer 1's kernel keeps two waves per SIMD, which the registers of a prefetched
+  // strip would not allow: it loads each strip at its start instead)
+  constexpr bool PF = MODE == THIN_OUT;
+  if constexpr (PF) strip_load(s0);
+  for (int sidx = s0; sidx < s1; ++sidx) {
+        __syncthreads();   // the previous strip's fragments have been read
+        if constexpr (!PF) strip_load(sidx);
+        strip_store();
         __syncthreads();
+        if constexpr (PF) strip_load(sidx + 1);   // (past the range: zeros, nothing loaded)
         const int j16 = 16 * wave + 8 * h;  // lane's 8 columns within the pass
         if constexpr (MODE == THIN_OUT) {
           // B_i[j'][v] = g[i][j' - v + 5]: thin LDS col (j' - v + 5) + 5 = j16 + e + 10 - v
@@ -641,8 +660,20 @@ __global__ __launch_bounds__(256) void conv_wgrad_thin_reduce_kernel(const float
   const int slot = idx % (11 * 352), ct = idx / (11 * 352);
   float s = 0.0f;
   if (idx < nslot) {
-    const float *p = partial + (long)ct * nchunk * 11 * 352 + slot;
-    for (int c = part; c < nchunk; c += RED_PARTS) s += p[(long)c * 11 * 352];
+    // four interleaved sums (partials c, c + 8, c + 16, c + 24 of each group of 32), so
+    // that four loads are in flight; the order is fixed, so the result is reproducible
+    const long st = (long)RED_PARTS * 11 * 352;
+    const float *q = partial + (long)ct * nchunk * 11 * 352 + slot + (long)part * 11 * 352;
+    float s0 = 0.0f, s1 = 0.0f, s2 = 0.0f, s3 = 0.0f;
+    int c = part;
+    for (; c + 3 * RED_PARTS < nchunk; c += 4 * RED_PARTS, q += 4 * st) {
+      s0 += q[0];
+      s1 += q[st];
+      s2 += q[2 * st];
+      s3 += q[3 * st];
+    }
+    for (; c < nchunk; c += RED_PARTS, q += st) s0 += q[0];
+    s = (s0 + s1) + (s2 + s3);
   }
   s = reduce_parts(s);
   if (part != 0 || idx >= nslot) return;
@@ -658,6 +689,7 @@ template <typename TT>
 hipError_t conv_wgrad_thin(int mode, const bf16 *wide, const TT *thin, int CW, float *partial, int nchunk, float *dw,
                            int B, int H, int W, hipStream_t s) {
   const int blocks = (CW / 32) * nchunk;
+  if ((long)B * H * W >= (1L << 31)) return hipErrorInvalidValue;   // strip indices are 32-bit
   if (mode == THIN_OUT)
     conv_wgrad_thin_kernel<THIN_OUT, TT><<<blocks, 256, 0, s>>>(wide, thin, CW, partial, B, H, W, nchunk);
   else
