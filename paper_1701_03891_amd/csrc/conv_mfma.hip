@@ -1060,7 +1060,7 @@ hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, in
   // BF16 with 32 outputs: 4 waves x 8 rows on a 32 x 32 tile, two 56 KiB slice buffers,
   // the next slice loaded into registers while this one computes.  Other types: 4 waves,
   // one buffer.
-  constexpr int ROWS = COUT == 32 ? 8 : 4;
+  constexpr int ROWS = COUT == 32 || sizeof(T) == 2 ? 8 : 4;
   constexpr int WAVES = 4;
   constexpr bool ASYNC = sizeof(T) == 2 && COUT == 32;
   int tw, tpi;
