@@ -1058,8 +1058,9 @@ hipError_t conv_mid(const T *in, const T *wp, const float *bias, int bias_pp, in
                     TO *out, int B, int H, int W, hipStream_t s, float oscale) {
   if (B <= 0) return hipSuccess;
   // BF16 with 32 outputs: 4 waves x 8 rows on a 32 x 32 tile, two 56 KiB slice buffers,
-  // the next slice loaded into registers while this one computes.  Other types: 4 waves,
-  // one buffer.
+  // the next slice loaded into registers while this one computes.  BF16 with 64 outputs
+  // (the data gradient of layer 2): 4 waves x 8 rows x 64 channels (256 accumulator
+  // registers), one buffer.  FP32 and FP8: 4 waves, one buffer.
   constexpr int ROWS = COUT == 32 || sizeof(T) == 2 ? 8 : 4;
   constexpr int WAVES = 4;
   constexpr bool ASYNC = sizeof(T) == 2 && COUT == 32;
