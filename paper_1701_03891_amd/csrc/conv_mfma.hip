@@ -717,7 +717,8 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
 }
 
 // ==================================================================== conv_last
-// CIN channels -> one output channel, as a banded-Toeplitz GEMM on 16x16 MFMAs.
+// CIN channels -> one output channel.  BF16 uses conv_last_rows_kernel (further below);
+// FP32 computes it as a banded-Toeplitz GEMM on 16x16 MFMAs:
 // A wave owns 16 output rows x 16 output columns.  For horizontal tap v and
 // each of the 26 input rows r of its halo:
 //     D[j][i] += sum_c in[c][r][j + v - 5] * W[c][u = r - i][v]   (0 <= u <= 10)
@@ -826,197 +827,123 @@ __global__ __launch_bounds__(256) void conv_last_kernel(const T *__restrict__ in
   }
 }
 
-// Value of lane n + S of the same 16-lane row (S > 0: DPP row_shl:S, S < 0:
-// row_shr:-S), zero where that lane falls outside the row.  S must fold to a
-// constant (the callers' loops are fully unrolled): DPP controls are immediates.
-DSI_INLINE int band_shift(int x, int S) {
-  switch (S) {
-    case 1: return __builtin_amdgcn_update_dpp(0, x, 0x101, 0xf, 0xf, true);
-    case -1: return __builtin_amdgcn_update_dpp(0, x, 0x111, 0xf, 0xf, true);
-    case 2: return __builtin_amdgcn_update_dpp(0, x, 0x102, 0xf, 0xf, true);
-    case -2: return __builtin_amdgcn_update_dpp(0, x, 0x112, 0xf, 0xf, true);
-    case 3: return __builtin_amdgcn_update_dpp(0, x, 0x103, 0xf, 0xf, true);
-    case -3: return __builtin_amdgcn_update_dpp(0, x, 0x113, 0xf, 0xf, true);
-    case 4: return __builtin_amdgcn_update_dpp(0, x, 0x104, 0xf, 0xf, true);
-    case -4: return __builtin_amdgcn_update_dpp(0, x, 0x114, 0xf, 0xf, true);
-    case 5: return __builtin_amdgcn_update_dpp(0, x, 0x105, 0xf, 0xf, true);
-    case -5: return __builtin_amdgcn_update_dpp(0, x, 0x115, 0xf, 0xf, true);
-    case 6: return __builtin_amdgcn_update_dpp(0, x, 0x106, 0xf, 0xf, true);
-    case -6: return __builtin_amdgcn_update_dpp(0, x, 0x116, 0xf, 0xf, true);
-    case 7: return __builtin_amdgcn_update_dpp(0, x, 0x107, 0xf, 0xf, true);
-    case -7: return __builtin_amdgcn_update_dpp(0, x, 0x117, 0xf, 0xf, true);
-    case 8: return __builtin_amdgcn_update_dpp(0, x, 0x108, 0xf, 0xf, true);
-    case -8: return __builtin_amdgcn_update_dpp(0, x, 0x118, 0xf, 0xf, true);
-    case 9: return __builtin_amdgcn_update_dpp(0, x, 0x109, 0xf, 0xf, true);
-    case -9: return __builtin_amdgcn_update_dpp(0, x, 0x119, 0xf, 0xf, true);
-    case 10: return __builtin_amdgcn_update_dpp(0, x, 0x10a, 0xf, 0xf, true);
-    case -10: return __builtin_amdgcn_update_dpp(0, x, 0x11a, 0xf, 0xf, true);
-    case 11: return __builtin_amdgcn_update_dpp(0, x, 0x10b, 0xf, 0xf, true);
-    case -11: return __builtin_amdgcn_update_dpp(0, x, 0x11b, 0xf, 0xf, true);
-    case 12: return __builtin_amdgcn_update_dpp(0, x, 0x10c, 0xf, 0xf, true);
-    case -12: return __builtin_amdgcn_update_dpp(0, x, 0x11c, 0xf, 0xf, true);
-    case 13: return __builtin_amdgcn_update_dpp(0, x, 0x10d, 0xf, 0xf, true);
-    case -13: return __builtin_amdgcn_update_dpp(0, x, 0x11d, 0xf, 0xf, true);
-    case 14: return __builtin_amdgcn_update_dpp(0, x, 0x10e, 0xf, 0xf, true);
-    case -14: return __builtin_amdgcn_update_dpp(0, x, 0x11e, 0xf, 0xf, true);
-    case 15: return __builtin_amdgcn_update_dpp(0, x, 0x10f, 0xf, 0xf, true);
-    case -15: return __builtin_amdgcn_update_dpp(0, x, 0x11f, 0xf, 0xf, true);
-    default: return x;
-  }
-}
-
-// BF16 variant: one 8-channel half-slice per pass and K = 32 packing four horizontal
-// taps (v = 4p .. 4p + 3) x 8 channels, so a pass holds 16 bytes per pixel in LDS (31 KiB
-// per 16 x 64 tile).  Two pass buffers: while one pass walks, each thread loads its units
-// of the next pass into registers and stores them into the other buffer at the end (two
-// blocks per CU still fit).  Lane group g = l/16 holds K slots 8g .. 8g+7: channels
-// 0 .. 7 of the pass at tap v = 4p + g.  The third quad's last tap (v = 11) has a zero
-// weight band; its activations come from one extra LDS column that is zero-filled.
-// wt [11 v][11 u][CIN] (bf16), staged in LDS with a zero v = 11 plane.
-template <int CIN>
-__global__ __launch_bounds__(256) void conv_last_bf16_kernel(const bf16 *__restrict__ in, const bf16 *__restrict__ wt,
-                                                             const float *__restrict__ bias, int bias_pp, int relu,
-                                                             float *__restrict__ out, int H, int W, int tiles_w,
-                                                             int tiles_per_img) {
-  constexpr int TH = 16, TW = 64, LH = TH + 2 * RAD, LW = TW + 2 * RAD + 1;
-  constexpr int NQ = (KT + 3) / 4;          // tap quads
-  constexpr int ROWB = LW * 16;             // bytes per LDS row: 8-channel pixels
-  constexpr int BUF = LH * ROWB;            // bytes per pass buffer
-  constexpr int NS = CIN / 8;               // 8-channel passes
-  constexpr int NU = LH * LW;               // 16-byte units per pass
-  constexpr int NPF = (NU + 255) / 256;     // units per thread per pass
-  __shared__ __attribute__((aligned(16))) unsigned char lds[2 * BUF];
-  __shared__ __attribute__((aligned(16))) bf16 wl[(KT + 1) * KT * CIN];
-  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n = lane & 15;
-  // tiles of one image (whose halos overlap) on one XCD, side by side in time
-  const int tl = xcd_logical(blockIdx.x, gridDim.x);
-  const int img = tl / tiles_per_img, t = tl % tiles_per_img;
-  const int bi0 = (t / tiles_w) * TH, bj0 = (t % tiles_w) * TW;
-  // unit k of this thread in pass sl: pixel (row, col) of the tile, channels 8 sl .. 8 sl + 7
-  // (zero outside the image and in the last column)
-  auto unit_load = [&](int sl, int k) -> i32x4 {
-    const int u = tid + 256 * k;
-    const int row = u / LW, col = u - row * LW;
-    const int gi = bi0 - RAD + row, gj = bj0 - RAD + col;
-    i32x4 v = {0, 0, 0, 0};
-    if (u < NU && col < LW - 1 && gi >= 0 && gi < H && gj >= 0 && gj < W)
-      v = *reinterpret_cast<const i32x4 *>(in + (((long)img * (CIN / 16) + sl / 2) * H * W + (long)gi * W + gj) * 16 +
-                                           (sl & 1) * 8);
-    return v;
-  };
-  {
-    // weights as 16-byte units, every load issued before the stores (the v = 11 plane zero);
-    // with them, the first pass
-    constexpr int NWU = (KT + 1) * KT * CIN / 8, NWL = KT * KT * CIN / 8, NIT = (NWU + 255) / 256;
-    i32x4 wv[NIT], pf[NPF];
-#pragma unroll
-    for (int k = 0; k < NIT; ++k) {
-      const int idx = tid + 256 * k;
-      wv[k] = idx < NWL ? *reinterpret_cast<const i32x4 *>(wt + idx * 8) : i32x4{0, 0, 0, 0};
-    }
-#pragma unroll
-    for (int k = 0; k < NPF; ++k) pf[k] = unit_load(0, k);
-#pragma unroll
-    for (int k = 0; k < NIT; ++k)
-      if (tid + 256 * k < NWU) *reinterpret_cast<i32x4 *>(wl + (tid + 256 * k) * 8) = wv[k];
-#pragma unroll
-    for (int k = 0; k < NPF; ++k)
-      if (tid + 256 * k < NU) *reinterpret_cast<i32x4 *>(lds + (tid + 256 * k) * 16) = pf[k];
-    __syncthreads();
-  }
-  // this lane's outputs: row n, columns 4g .. 4g+3 of the wave's 16; their biases are
-  // loaded now, so the epilogue waits for nothing
-  const int go = bi0 + n, gj0 = bj0 + wave * 16 + 4 * g;
-  float bv[4] = {0.0f, 0.0f, 0.0f, 0.0f};
-  if (bias && go < H) {
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (gj0 + e < W) bv[e] = bias_pp ? bias[(long)go * W + gj0 + e] : bias[0];
-  }
-  f32x4 acc[NQ];
-#pragma unroll
-  for (int p = 0; p < NQ; ++p) acc[p] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
-  for (int sl = 0; sl < NS; ++sl) {
-    const unsigned char *buf = lds + (sl & 1) * BUF;
-    unsigned char *nbuf = lds + ((sl + 1) & 1) * BUF;   // unread during this pass
-    // the next pass's units, in flight during the walk
-    i32x4 pf[NPF];
-    const bool more = sl + 1 < NS;
-#pragma unroll
-    for (int k = 0; k < NPF; ++k) pf[k] = more ? unit_load(sl + 1, k) : i32x4{0, 0, 0, 0};
-    // Band operand of quad p at input row r: B[k][i] = W[c][u = r - i][v], zero outside
-    // 0 <= u <= 10.  It is one register z[p] moved across lanes: lane n of each 16-lane
-    // group holds W[u = 10 - n] (zero for n > 10), so B at row r is z shifted by 10 - r
-    // lanes (DPP row_shl:10-r for r < 10, row_shr:r-10 for r > 10, zeros shifted in).
-    i32x4 z[NQ];
-    const bf16 *whead = wl + g * KT * CIN + sl * 8;
-#pragma unroll
-    for (int p = 0; p < NQ; ++p) {
-      const i32x4 w = *reinterpret_cast<const i32x4 *>(whead + (4 * p * KT + KT - 1 - min(n, KT - 1)) * CIN);
-      z[p] = n < KT ? w : i32x4{0, 0, 0, 0};
-    }
-    // The pass is one walk of LH x NQ (row, tap quad) steps.  Each step's activation
-    // fragment is read LA steps ahead, and a scheduling barrier after every step keeps the
-    // reads there, so the LDS latency hides behind the MFMAs between.
-    const unsigned char *abase = buf + (wave * 16 + n + g) * 16;   // this lane's pixel for quad 0
-    constexpr int NST = LH * NQ, LA = 4;
-    auto afrag = [&](int st) {
-      Frag8<bf16> a;
-      a.v = *reinterpret_cast<const bf16x8 *>(abase + (st / NQ) * ROWB + 4 * (st % NQ) * 16);
-      return a;
-    };
-    Frag8<bf16> aq[LA];
-#pragma unroll
-    for (int q = 0; q < LA; ++q) aq[q] = afrag(q);
-#pragma unroll
-    for (int r = 0; r < LH; ++r) {
-#pragma unroll
-      for (int p = 0; p < NQ; ++p) {
-        const int st = r * NQ + p;
-        const Frag8<bf16> a = aq[st % LA];
-        if (st + LA < NST) aq[st % LA] = afrag(st + LA);
-        i32x4 band;
-#pragma unroll
-        for (int q = 0; q < 4; ++q) band[q] = band_shift(z[p][q], KT - 1 - r);
-        Frag8<bf16> b;
-        __builtin_memcpy(&b, &band, 16);
-        acc[p] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc[p], 0, 0, 0);
-        __builtin_amdgcn_sched_barrier(0);
-      }
-    }
-    if (more) {
-#pragma unroll
-      for (int k = 0; k < NPF; ++k)
-        if (tid + 256 * k < NU) *reinterpret_cast<i32x4 *>(nbuf + (tid + 256 * k) * 16) = pf[k];
-    }
-    __syncthreads();   // the next pass is in place and every wave is done with this one
-  }
-  f32x4 accs = acc[0];
-#pragma unroll
-  for (int p = 1; p < NQ; ++p) accs += acc[p];
-  if (go >= H) return;
-  float v[4];
-#pragma unroll
-  for (int e = 0; e < 4; ++e) {
-    v[e] = accs[e] + bv[e];
-    if (relu) v[e] = fmaxf(v[e], 0.0f);
-  }
-  float *dst = out + ((long)img * H + go) * W + gj0;
-  if (W % 4 == 0 && gj0 + 3 < W) {
-    *reinterpret_cast<f32x4 *>(dst) = f32x4{v[0], v[1], v[2], v[3]};
-  } else {
-#pragma unroll
-    for (int e = 0; e < 4; ++e)
-      if (gj0 + e < W) dst[e] = v[e];
-  }
-}
-
 template <> DSI_INLINE void mma16<bf16>(const Frag8<bf16> &a, const Frag8<bf16> &b, f32x4 &acc) {
   acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a.v, b.v, acc, 0, 0, 0);
 }
 template <> DSI_INLINE void mma16<float>(const Frag8<float> &a, const Frag8<float> &b, f32x4 &acc) {
 #pragma unroll
   for (int e = 0; e < 4; ++e) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(a.lo[e], b.lo[e], acc, 0, 0, 0);
+}
+
+// BF16 conv3 by rows: for each tap column v the partial sums over channels and filter
+// rows, Q[i][j'][v] = sum_{c,u} W[c][u][v] a[c][i+u-5][j'], come from
+// v_mfma_f32_16x16x32_bf16 with M = 16 input columns, N = v (11 of 16 used) and K = 32
+// channels of one input row; the output is the column shift out[i][j] = sum_v
+// Q[i][j+v-5][v] (+ bias).  A block owns 16 NWV input columns (16 NWV - 10 output columns)
+// and a band of output rows of one image; wave w owns input columns 16w .. 16w + 15.
+// A wave walks the input rows once: each row's activation fragment (lane: one pixel, 8
+// consecutive channels: 16 bytes of the channel-blocked tensor) is loaded 11 rows ahead
+// straight into registers and feeds 11 MFMAs, one per filter row u, into the accumulators
+// of output rows r - u + 5 (11 rotating accumulators).  When an output row is complete the
+// waves put their Q tiles in LDS and, after one barrier, a thread per output column adds
+// its 11 shifted values.  in [B][CIN/16][H][W][16]; wt [11 v][11 u][CIN]; out [B][H][W].
+template <int CIN, int NWV, int RB>
+__global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__restrict__ in,
+                                                                  const bf16 *__restrict__ wt,
+                                                                  const float *__restrict__ bias, int bias_pp,
+                                                                  int relu, float *__restrict__ out, int H, int W,
+                                                                  int col_tiles, int row_tiles) {
+  constexpr int NKS = CIN / 32, NIN = 16 * NWV, NOUT = NIN - 10, QS = 17, RG = 4;
+  static_assert(RG * NOUT <= 64 * NWV, "one thread per output of a row group");
+  __shared__ float qs[2][RG][NIN * QS];
+  __shared__ float bs[RB * NOUT];   // the block's per-pixel biases (loaded once)
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n16 = lane & 15;
+  const int rt = blockIdx.x % row_tiles, ct = (blockIdx.x / row_tiles) % col_tiles;
+  const int b = blockIdx.x / (row_tiles * col_tiles);
+  const int I0 = rt * RB, I1 = min(I0 + RB, H), J0 = ct * NOUT;
+  const int NR = I1 - I0 + 10;   // input rows I0 - 5 .. I1 + 4
+
+  // B operands: lane (v = n16, channel group g) holds W[32 ks + 8g + e][u][v], zero for v = 11..15
+  Frag8<bf16> wf[11][NKS];
+#pragma unroll
+  for (int u = 0; u < 11; ++u)
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) {
+      wf[u][ks] = frag_zero<bf16>();
+      if (n16 < 11) wf[u][ks] = frag_load<bf16>(wt + (n16 * 11 + u) * CIN + 32 * ks + 8 * g);
+    }
+  // A operand source: input column j (M index n16), channels 32 ks + 8g .. + 7
+  const int jc = J0 - 5 + 16 * wave + n16;
+  const bool colok = jc >= 0 && jc < W;
+  const bf16 *src = in + (((long)b * (CIN / 16) + (g >> 1)) * H * W + (colok ? jc : 0)) * 16 + 8 * (g & 1);
+  auto a_load = [&](int t, int ks) {
+    const int r = I0 - 5 + t;
+    Frag8<bf16> f = frag_zero<bf16>();
+    if (colok && r >= 0 && r < H) f = frag_load<bf16>(src + ((long)(2 * ks) * H + r) * W * 16);
+    return f;
+  };
+  Frag8<bf16> aq[11][NKS];
+#pragma unroll
+  for (int k = 0; k < 11; ++k)
+#pragma unroll
+    for (int ks = 0; ks < NKS; ++ks) aq[k][ks] = a_load(k, ks);
+  f32x4 acc[11];
+#pragma unroll
+  for (int k = 0; k < 11; ++k) acc[k] = f32x4{0.0f, 0.0f, 0.0f, 0.0f};
+
+  // the reducing thread's row within a group of RG output rows, its output column
+  const int rg = tid / NOUT, jt = tid - rg * NOUT, jo = J0 + jt;
+  const bool io_ok = rg < RG && jo < W;
+  const float b0 = bias && !bias_pp ? bias[0] : 0.0f;
+  if (bias && bias_pp) {   // (read after the first reduction's barrier)
+    for (int idx = tid; idx < RB * NOUT; idx += 64 * NWV) {
+      const int r = idx / NOUT, c = idx - r * NOUT, i = I0 + r, j = J0 + c;
+      bs[idx] = i < I1 && j < W ? bias[(long)i * W + j] : 0.0f;
+    }
+  }
+  for (int t0 = 0; t0 < NR; t0 += 11) {
+    static_for<11>([&](auto kc) {
+      constexpr int k = decltype(kc)::value;
+      const int t = t0 + k;
+      if (t < NR) {
+        // filter row u of input row t reaches output row I0 + t - u: its accumulator is
+        // (k - u) mod 11 (t = k mod 11), and u = 0 starts that row
+#pragma unroll
+        for (int ks = 0; ks < NKS; ++ks)
+#pragma unroll
+          for (int u = 0; u < 11; ++u) {
+            const int slot = (k - u + 11) % 11;
+            const f32x4 c = (u == 0 && ks == 0) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : acc[slot];
+            acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[k][ks].v, wf[u][ks].v, c, 0, 0, 0);
+          }
+        // the ring slot of row t now takes row t + 11
+        if (t + 11 < NR) {
+#pragma unroll
+          for (int ks = 0; ks < NKS; ++ks) aq[k][ks] = a_load(t + 11, ks);
+        }
+        if (t >= 10) {   // output row I0 + t - 10 is complete in accumulator (k + 1) mod 11
+          constexpr int done = (k + 1) % 11;
+          const int orow = t - 10, grp = orow / RG;
+          float *q = qs[grp & 1][orow - grp * RG];
+          // lane (v = n16, g) holds input columns 16 wave + 4g + e of tap column v
+#pragma unroll
+          for (int e = 0; e < 4; ++e) q[(16 * wave + 4 * g + e) * QS + n16] = acc[done][e];
+          // every RG rows (and after the last) the threads add up the group's outputs
+          if (orow - grp * RG == RG - 1 || t == NR - 1) {
+            __syncthreads();
+            const int i = I0 + grp * RG + rg;
+            if (io_ok && i < I1) {
+              const float *qr = qs[grp & 1][rg];
+              float s = bias ? (bias_pp ? bs[(i - I0) * NOUT + jt] : b0) : 0.0f;
+#pragma unroll
+              for (int v = 0; v < 11; ++v) s += qr[(jt + v) * QS + v];
+              out[((long)b * H + i) * W + jo] = relu ? fmaxf(s, 0.0f) : s;
+            }
+          }
+        }
+      }
+    });
+  }
 }
 
 // ==================================================================== launchers
@@ -1082,12 +1009,19 @@ template <typename T, int CIN>
 hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, int relu, float *out, int B,
                      int H, int W, hipStream_t s) {
   if (B <= 0) return hipSuccess;
-  int tw, tpi;
-  tiles(H, W, 16, 64, tw, tpi);
-  if constexpr (sizeof(T) == 2)
-    conv_last_bf16_kernel<CIN><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
-  else
+  if constexpr (sizeof(T) == 2) {
+    // 5 waves: 80 input columns, 70 output columns per block; bands of 64 output rows
+    constexpr int NWV = 5, NOUT = 16 * NWV - 10, RB = 64;
+    const int col_tiles = (W + NOUT - 1) / NOUT, row_tiles = (H + RB - 1) / RB;
+    const long blocks = (long)B * col_tiles * row_tiles;
+    if (blocks >= (1L << 31)) return hipErrorInvalidValue;
+    conv_last_rows_kernel<CIN, NWV, RB><<<(unsigned)blocks, 64 * NWV, 0, s>>>(in, w, bias, bias_pp, relu, out, H,
+                                                                             W, col_tiles, row_tiles);
+  } else {
+    int tw, tpi;
+    tiles(H, W, 16, 64, tw, tpi);
     conv_last_kernel<T, CIN><<<B * tpi, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W, tw, tpi);
+  }
   return hipGetLastError();
 }
 
