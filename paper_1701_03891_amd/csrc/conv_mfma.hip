@@ -579,6 +579,13 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   const int a0 = px + 8 * h + OFF, odd = NCOPY == 2 ? (a0 & 1) : 0;
   const T *trow0 = tile + odd * COPY + wave * LWA + a0 - odd;
 
+  // 2-byte outputs: an image's four 16-byte stores per lane are issued during the next
+  // image's MFMAs (then the last image's after the loop), so the stores stream out
+  // between the matrix instructions instead of stalling the wave in a burst
+  constexpr bool PIPE = sizeof(TO) == 2;
+  i32x4 pend[2 * NCT];
+  TO *pend_img = out;
+  bool pend_live = false;
   for (int im = 0; im < nimg; ++im) {
     const long obase = (long)(img0 + im) * img_stride;   // uniform: the stores take it as a scalar base
     TO *const oimg = out + obase;
@@ -621,6 +628,17 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
           wf.mma(xf, acc[c]);
         }
       }
+      if constexpr (PIPE) {
+        if (u >= 1 && u <= 2 * NCT && pend_live) {
+          const int j = u - 1;
+          *reinterpret_cast<i32x4 *>(pend_img + ooff[j >> 1][2 * (j & 1)] + 4 * h) = pend[j];
+        }
+        __builtin_amdgcn_sched_barrier(0);
+      }
+    }
+    if constexpr (PIPE) {
+      pend_img = oimg;
+      pend_live = live;
     }
     if (!live) continue;   // (the lanes px and px + 32 of a pixel are live together)
     if constexpr (sizeof(TO) == 2) {
@@ -655,7 +673,8 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
             pb[k] = (int)sw[1];
           }
           // slice 2c + qp, channels 8h.. of the pixel: the q-even group's offset plus 4h
-          *reinterpret_cast<i32x4 *>(oimg + ooff[c][2 * qp] + 4 * h) = i32x4{pa[0], pa[1], pb[0], pb[1]};
+          // (stored during the next image's MFMAs)
+          pend[2 * c + qp] = i32x4{pa[0], pa[1], pb[0], pb[1]};
         }
       continue;
     }
@@ -713,6 +732,13 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         }
         store4<TO>(dst, vals[0], vals[1], vals[2], vals[3]);
       }
+  }
+  if constexpr (PIPE) {   // the last image's stores
+    if (pend_live) {
+#pragma unroll
+      for (int j = 0; j < 2 * NCT; ++j)
+        *reinterpret_cast<i32x4 *>(pend_img + ooff[j >> 1][2 * (j & 1)] + 4 * h) = pend[j];
+    }
   }
 }
 
