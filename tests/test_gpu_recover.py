@@ -94,6 +94,20 @@ def test_recover_ragged_tiles(dsi, prec, bias_per_pixel):
     assert err.max() <= TOL[prec]
 
 
+@pytest.mark.parametrize("bias_per_pixel", [True, False])
+def test_recover_conv3_row_bands_and_column_tiles(dsi, bias_per_pixel):
+    """70 x 152 images: BF16 conv3 works in 64-row bands of 70 output columns, so this
+    is a full and a 6-row band, and two full and one 12-column tile (each reading 5
+    columns beyond its edges); batch 2, M = 600, every pixel against the FP64 oracle."""
+    P, ctx = dsi
+    case = make_case(70, 152, 600, 2, cfg_id=13, bias_per_pixel=bias_per_pixel, bias_std=0.05)
+    ref = case.oracle_forward()
+    got = _recover(P, ctx, case, "bf16")
+    err = relerr_per_image(got, ref)
+    print(f"conv3 bands/tiles bf16 bias_pp={bias_per_pixel}: max rel err {err.max():.3e}")
+    assert err.max() <= TOL["bf16"]
+
+
 def test_recover_uneven_tiles_per_block(dsi):
     """BF16 conv2 runs one block per CU over every G-th tile: 40x48 images, batch 100 give
     400 tiles, so some blocks run two tiles (prefetching the second's first slice) and
