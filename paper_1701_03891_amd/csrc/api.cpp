@@ -505,9 +505,9 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
   return DSI_OK;
 }
 
-// image chunks (blocks per (ci tile, tap column) pair) of the weight-gradient kernels:
-// the conv2 kernel has 22 such pairs and one block per CU fits, so 23 chunks make two
-// even rounds of 506 blocks on 256 CUs; the single-channel ones have 1-2 pairs
+// image chunks (blocks per (ci tile, tap column) pair) of the blocked conv2 weight-gradient
+// kernel (widths W % 8 != 0): 22 such pairs and one block per CU, so 23 chunks make two
+// even rounds of 506 blocks on 256 CUs
 int wgrad_chunks(int B) { return std::max(1, std::min(B, 23)); }
 // strip ranges of the single-channel-side kernels (8 x 64 strips): 256 per 32-channel
 // tile, one block per CU for layer 3's 32 channels, two for layer 1's 64
