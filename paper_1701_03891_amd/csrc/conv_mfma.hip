@@ -870,9 +870,10 @@ template <> DSI_INLINE void mma16<float>(const Frag8<float> &a, const Frag8<floa
 // A wave walks the input rows once: each row's activation fragment (lane: one pixel, 8
 // consecutive channels: 16 bytes of the channel-blocked tensor) is loaded 11 rows ahead
 // straight into registers and feeds 11 MFMAs, one per filter row u, into the accumulators
-// of output rows r - u + 5 (11 rotating accumulators).  When an output row is complete the
-// waves put their Q tiles in LDS and, after one barrier, a thread per output column adds
-// its 11 shifted values.  in [B][CIN/16][H][W][16]; wt [11 v][11 u][CIN]; out [B][H][W].
+// of output rows r - u + 5 (11 rotating accumulators).  As output rows complete, the waves
+// put their Q tiles in LDS; every RG rows, after one barrier, a thread per output adds its
+// 11 shifted values and the bias (per-pixel biases staged in LDS once).
+// in [B][CIN/16][H][W][16]; wt [11 v][11 u][CIN]; out [B][H][W].
 template <int CIN, int NWV, int RB>
 __global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__restrict__ in,
                                                                   const bf16 *__restrict__ wt,
