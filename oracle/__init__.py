@@ -71,6 +71,9 @@ def lib():
             "orc_dct_matrix": (None, [i, P]),
             "orc_spectral_norm": (d, [P, i, i, i]),
             "orc_ista_dct": (i, [P, P, i, i, i, i, i, d, P, P]),
+            "orc_round": (d, [d, i]),
+            "orc_quantize": (None, [P, P, l_, i, d]),
+            "orc_forward_q": (None, [P, P, P, P, P, i, P, P, P]),
         }
         for name, (res, args) in sig.items():
             f = getattr(L, name)
@@ -242,6 +245,100 @@ def forward(net: Net, wfc, w, b, y, return_acts=False):
             off += sz
         out.append(a)
     return xhat, out
+
+
+# ------------------------------------------------ reduced-precision operands
+Q_NONE, Q_BF16, Q_E4M3 = 0, 1, 2
+
+
+class _Q(ctypes.Structure):
+    _fields_ = [("fmt", ctypes.c_int), ("scale", ctypes.c_double)]
+
+
+class _Quant(ctypes.Structure):
+    _fields_ = [("y", _Q), ("wfc", _Q), ("xt", _Q), ("w", _Q * 8), ("a", _Q * 8),
+                ("acc_fp32", ctypes.c_int)]
+
+
+@dataclass
+class Quant:
+    """Where a reduced-precision forward pass rounds its operands: each point is
+    (format, scale), a value v being stored as round(v / scale) * scale.  Points:
+    y, the FC weights W_fc, the proxy x~, the weights w[l] of conv layer l and the
+    output a[l] of conv layer l.  acc_fp32 adds FP32 accumulation to the error model."""
+
+    y: tuple = (Q_NONE, 1.0)
+    wfc: tuple = (Q_NONE, 1.0)
+    xt: tuple = (Q_NONE, 1.0)
+    w: list = field(default_factory=lambda: [(Q_NONE, 1.0)] * 8)
+    a: list = field(default_factory=lambda: [(Q_NONE, 1.0)] * 8)
+    acc_fp32: bool = False
+
+    def _c(self) -> _Quant:
+        q = _Quant()
+        for name in ("y", "wfc", "xt"):
+            f, sc = getattr(self, name)
+            setattr(q, name, _Q(int(f), float(sc)))
+        for l in range(8):
+            q.w[l] = _Q(int(self.w[l][0]), float(self.w[l][1]))
+            q.a[l] = _Q(int(self.a[l][0]), float(self.a[l][1]))
+        q.acc_fp32 = int(self.acc_fp32)
+        return q
+
+    @staticmethod
+    def fp32(L=3) -> "Quant":
+        """FP32 operands, FP32 accumulation (no operand rounding: the inputs are FP32 values)."""
+        return Quant(acc_fp32=True)
+
+    @staticmethod
+    def bf16(L=3) -> "Quant":
+        """BF16 variant: y, W_fc and every conv weight are rounded to BF16 before use, the
+        proxy x~ and every hidden layer's output after it is computed; sums in FP32 and
+        the network's output is FP32."""
+        b = (Q_BF16, 1.0)
+        return Quant(y=b, wfc=b, xt=b, w=[b] * L + [(Q_NONE, 1.0)] * (8 - L),
+                     a=[b] * (L - 1) + [(Q_NONE, 1.0)] * (9 - L), acc_fp32=True)
+
+    @staticmethod
+    def fp8(s_y, s_fc, s_a1, s_w2) -> "Quant":
+        """FP8 variant of the paper's network: the proxy layer and conv layer 2 take e4m3
+        operands with power-of-two per-tensor scales (y: s_y, W_fc: s_fc, conv layer 1's
+        output: s_a1, W2: s_w2); conv layers 1 and 3 take BF16 operands, x~ and conv
+        layer 2's output are stored in BF16; sums in FP32."""
+        b, e = (Q_BF16, 1.0), Q_E4M3
+        none = (Q_NONE, 1.0)
+        return Quant(y=(e, s_y), wfc=(e, s_fc), xt=b, w=[b, (e, s_w2), b] + [none] * 5,
+                     a=[(e, s_a1), b] + [none] * 6, acc_fp32=True)
+
+
+def round_fmt(x, fmt):
+    """Round each value to the nearest value of format fmt (ties to even; e4m3 saturating)."""
+    x = np.asarray(x, dtype=np.float64)
+    return np.vectorize(lambda v: lib().orc_round(float(v), int(fmt)), otypes=[np.float64])(x)
+
+
+def quantize(x, fmt, scale=1.0):
+    """round(x / scale) * scale elementwise."""
+    x = _c(x)
+    out = np.empty_like(x)
+    lib().orc_quantize(_p(x), _p(out), x.size, int(fmt), float(scale))
+    return out
+
+
+def forward_q(net: Net, wfc, w, b, y, quant: Quant, want_sigma=False):
+    """The forward map (Sec. 4, Eq. 1) with operands rounded at the points of ``quant``
+    (exact sums).  With ``want_sigma`` also returns the modelled standard deviation of
+    each output pixel's error against the exact map (see orc.h)."""
+    wfc, y = _c(wfc), _c(y)
+    ws, bs = _params_c(net, w, b)
+    B = y.shape[0]
+    N = net.n1 * net.n2
+    xhat = np.empty((B, N))
+    sig = np.empty((B, N)) if want_sigma else None
+    cn, cq = net._c(), quant._c()
+    lib().orc_forward_q(ctypes.byref(cn), _p(wfc), _ptr_array(ws), _ptr_array(bs), _p(y), B,
+                        ctypes.byref(cq), _p(xhat), _p(sig) if sig is not None else None)
+    return (xhat, sig) if want_sigma else xhat
 
 
 def loss(xhat, x):

@@ -130,6 +130,180 @@ void orc_forward(const orc_net *net, const double *wfc, const double *const *w,
   }
 }
 
+/* ------------------------------------------- reduced-precision operands (BF16, FP8) */
+/* Rounding to a binary floating-point format, from its definition: p significand bits
+ * (the leading one included), normal numbers from 2^emin up (below that the spacing
+ * stays 2^(emin - p + 1): the subnormals), largest finite value maxv.  The result is the
+ * nearest representable value; a tie goes to the one with an even last significand
+ * bit.  With sat, magnitudes from maxv up give +-maxv (the clamp that precedes a
+ * saturating conversion); without it a value that rounds past maxv becomes +-inf. */
+static double round_format(double v, int p, int emin, double maxv, int sat) {
+  if (v == 0.0 || v != v) return v;
+  double a = fabs(v);
+  if (sat && a >= maxv) return copysign(maxv, v);
+  int e;
+  frexp(a, &e);                /* a = f 2^e with f in [0.5, 1): leading bit 2^(e-1) */
+  int E = e - 1 < emin ? emin : e - 1;
+  double q = ldexp(1.0, E - p + 1);      /* spacing of representable values at a */
+  double n = a / q;                      /* exact: q is a power of two */
+  double fl = floor(n), d = n - fl;
+  if (d > 0.5 || (d == 0.5 && fmod(fl, 2.0) != 0.0)) fl += 1.0;
+  double r = fl * q;
+  if (r > maxv) r = sat ? maxv : INFINITY;
+  return copysign(r, v);
+}
+
+/* spacing of the format's values at magnitude |v| (the unit in the last place) */
+static double ulp_format(double v, int p, int emin) {
+  double a = fabs(v);
+  int e;
+  if (a == 0.0) return ldexp(1.0, emin - p + 1);
+  frexp(a, &e);
+  int E = e - 1 < emin ? emin : e - 1;
+  return ldexp(1.0, E - p + 1);
+}
+
+/* BF16: 8 significand bits, the exponent range of FP32.  OCP FP8 e4m3 ("fn"): 4
+ * significand bits, normals from 2^-6, largest finite value 1.75 * 2^8 = 448. */
+#define BF16_MAX (255.0 * 1.329227995784916e+36)   /* (2 - 2^-7) 2^127 = 255 * 2^120 */
+double orc_round(double v, int fmt) {
+  if (fmt == ORC_Q_BF16) return round_format(v, 8, -126, BF16_MAX, 0);
+  if (fmt == ORC_Q_E4M3) return round_format(v, 4, -6, 448.0, 1);
+  return v;
+}
+
+static double q_value(double v, orc_q q) {
+  return q.fmt == ORC_Q_NONE ? v : orc_round(v / q.scale, q.fmt) * q.scale;
+}
+
+/* variance of the rounding error of v under q, modelled as uniform over one spacing:
+ * (scale * ulp(v / scale))^2 / 12 */
+static double q_var(double v, orc_q q) {
+  if (q.fmt == ORC_Q_NONE) return 0.0;
+  double u = q.fmt == ORC_Q_BF16 ? ulp_format(v / q.scale, 8, -126) : ulp_format(v / q.scale, 4, -6);
+  u *= q.scale;
+  return u * u / 12.0;
+}
+
+void orc_quantize(const double *x, double *out, long n, int fmt, double scale) {
+  orc_q q = {fmt, scale};
+  for (long i = 0; i < n; ++i) out[i] = q_value(x[i], q);
+}
+
+/* Variance of the error of an FP32 running sum of n terms, per unit of sum of
+ * squared terms: step t adds an error of variance at most ulp(S_t)^2 / 12 with
+ * ulp(S_t) <= 2^-23 |S_t|, and a sum of terms of random sign has E[S_t^2] =
+ * (t/n) sum_k term_k^2, so the n steps add (n / 24) 2^-46 sum_k term_k^2. */
+static double acc_var_coeff(int acc_fp32, long n) {
+  return acc_fp32 ? (double)n / 24.0 * ldexp(1.0, -46) : 0.0;
+}
+
+/* One image of the reduced-precision forward pass, and (var != NULL) the variance
+ * of each output pixel's error against the exact network, propagated linearly:
+ * a rounding error passes through a layer like a small input change (weights
+ * squared, ReLU passing it where the unit is active), and errors are taken as
+ * independent with the variances of q_var and acc_var_coeff. */
+static void forward_one_q(const orc_net *net, const double *wfcq, const double *wfcv,
+                          const double *const *wq, const double *const *wv, const double *const *b,
+                          const double *yb, const orc_quant *qs, double *act, double *var) {
+  const int N = net->n1 * net->n2, M = net->M, n1 = net->n1, n2 = net->n2;
+  double *a[9], *z[8];
+  acts_layout(net, act, a, z);
+  double *yq = (double *)malloc(sizeof(double) * M);
+  for (int m = 0; m < M; ++m) yq[m] = q_value(yb[m], qs->y);
+  orc_proxy(wfcq, yq, a[0], 1, M, N);
+  int cmax = 1;
+  for (int l = 0; l <= net->L; ++l) cmax = net->C[l] > cmax ? net->C[l] : cmax;
+  double *V = NULL, *Vn = NULL, *t1 = NULL, *t2 = NULL, *sq = NULL, *zero = NULL;
+  if (var) {
+    V = (double *)malloc(sizeof(double) * cmax * N);
+    Vn = (double *)malloc(sizeof(double) * cmax * N);
+    t1 = (double *)malloc(sizeof(double) * cmax * N);
+    t2 = (double *)malloc(sizeof(double) * cmax * N);
+    sq = (double *)malloc(sizeof(double) * cmax * N);
+    zero = (double *)calloc((size_t)cmax, sizeof(double));
+    /* proxy: rounding of y (through W^2), of W_fc (times y^2), of the sum, of x~ */
+    double *vy = (double *)malloc(sizeof(double) * M), *y2 = (double *)malloc(sizeof(double) * M);
+    double *w2 = (double *)malloc(sizeof(double) * (long)N * M);
+    double *wc = (double *)malloc(sizeof(double) * (long)N * M);
+    const double ca = acc_var_coeff(qs->acc_fp32, M);
+    for (int m = 0; m < M; ++m) { vy[m] = q_var(yb[m], qs->y); y2[m] = yq[m] * yq[m]; }
+    for (long i = 0; i < (long)N * M; ++i) { w2[i] = wfcq[i] * wfcq[i]; wc[i] = wfcv[i] + ca * w2[i]; }
+    orc_proxy(w2, vy, t1, 1, M, N);
+    orc_proxy(wc, y2, t2, 1, M, N);
+    for (int p = 0; p < N; ++p) V[p] = t1[p] + t2[p];
+    free(vy); free(y2); free(w2); free(wc);
+  }
+  for (int p = 0; p < N; ++p) {
+    double v = q_value(a[0][p], qs->xt);
+    if (var) V[p] += q_var(a[0][p], qs->xt);
+    a[0][p] = v;
+  }
+  for (int l = 0; l < net->L; ++l) {
+    const int relu = (l < net->L - 1) || net->relu_last;
+    const int Cin = net->C[l], Cout = net->C[l + 1], k = net->k[l];
+    const long nw = (long)Cout * Cin * k * k, no = (long)Cout * N;
+    orc_conv_layer(a[l], Cin, n1, n2, wq[l], Cout, k, b[l], net->bias_full, relu, z[l], a[l + 1]);
+    if (var) {
+      /* Vz = W^2 * V + (var(W) + c W^2) * a^2 */
+      double *w2 = (double *)malloc(sizeof(double) * nw), *wc = (double *)malloc(sizeof(double) * nw);
+      const double ca = acc_var_coeff(qs->acc_fp32, (long)Cin * k * k + 1);
+      for (long i = 0; i < nw; ++i) { w2[i] = wq[l][i] * wq[l][i]; wc[i] = wv[l][i] + ca * w2[i]; }
+      for (long i = 0; i < (long)Cin * N; ++i) sq[i] = a[l][i] * a[l][i];
+      orc_conv_layer(V, Cin, n1, n2, w2, Cout, k, zero, 0, 0, NULL, t1);
+      orc_conv_layer(sq, Cin, n1, n2, wc, Cout, k, zero, 0, 0, NULL, t2);
+      for (long i = 0; i < no; ++i) Vn[i] = (relu && !(a[l + 1][i] > 0.0)) ? 0.0 : t1[i] + t2[i];
+      free(w2); free(wc);
+    }
+    for (long i = 0; i < no; ++i) {
+      double v = q_value(a[l + 1][i], qs->a[l]);
+      if (var) Vn[i] += q_var(a[l + 1][i], qs->a[l]);
+      a[l + 1][i] = v;
+    }
+    if (var) { double *t = V; V = Vn; Vn = t; }
+  }
+  if (var) {
+    memcpy(var, V, sizeof(double) * N);
+    free(V); free(Vn); free(t1); free(t2); free(sq); free(zero);
+  }
+  free(yq);
+}
+
+void orc_forward_q(const orc_net *net, const double *wfc, const double *const *w,
+                   const double *const *b, const double *y, int B, const orc_quant *qs,
+                   double *xhat, double *sigma) {
+  const int N = net->n1 * net->n2, M = net->M, L = net->L;
+  const long per = orc_acts_per_image(net);
+  /* rounded weights and (for the error model) their rounding-error variances */
+  double *wfcq = (double *)malloc(sizeof(double) * (long)N * M);
+  double *wfcv = (double *)malloc(sizeof(double) * (long)N * M);
+  for (long i = 0; i < (long)N * M; ++i) { wfcq[i] = q_value(wfc[i], qs->wfc); wfcv[i] = q_var(wfc[i], qs->wfc); }
+  double *wq[8], *wv[8];
+  for (int l = 0; l < L; ++l) {
+    const long nw = (long)net->C[l + 1] * net->C[l] * net->k[l] * net->k[l];
+    wq[l] = (double *)malloc(sizeof(double) * nw);
+    wv[l] = (double *)malloc(sizeof(double) * nw);
+    for (long i = 0; i < nw; ++i) { wq[l][i] = q_value(w[l][i], qs->w[l]); wv[l][i] = q_var(w[l][i], qs->w[l]); }
+  }
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int bi = 0; bi < B; ++bi) {
+    double *act = (double *)malloc(sizeof(double) * per);
+    double *var = sigma ? (double *)malloc(sizeof(double) * N) : NULL;
+    forward_one_q(net, wfcq, wfcv, (const double *const *)wq, (const double *const *)wv, b,
+                  y + (long)bi * M, qs, act, var);
+    double *a[9], *z[8];
+    acts_layout(net, act, a, z);
+    memcpy(xhat + (long)bi * N, a[L], sizeof(double) * N);
+    if (sigma)
+      for (int p = 0; p < N; ++p) sigma[(long)bi * N + p] = sqrt(var[p]);
+    free(var);
+    free(act);
+  }
+  for (int l = 0; l < L; ++l) { free(wq[l]); free(wv[l]); }
+  free(wfcq);
+  free(wfcv);
+}
+
 /* ------------------------------------------------------------- Sec. 4 loss */
 double orc_loss(const double *xhat, const double *x, int B, int N, double *g) {
   double L = 0.0;

@@ -73,6 +73,34 @@ long orc_acts_per_image(const orc_net *net);
 void orc_forward(const orc_net *net, const double *wfc, const double *const *w,
                  const double *const *b, const double *y, int B, double *xhat, double *acts);
 
+/* Reduced-precision operands.  A quantisation point stores a value v as
+ * round(v / scale) * scale, round being round-to-nearest-even into the format
+ * (ORC_Q_BF16: 8 significand bits, the range of FP32; ORC_Q_E4M3: OCP FP8 e4m3fn,
+ * 4 significand bits, subnormals below 2^-6, saturating at +-448). */
+enum { ORC_Q_NONE = 0, ORC_Q_BF16 = 1, ORC_Q_E4M3 = 2 };
+typedef struct { int fmt; double scale; } orc_q;
+typedef struct {
+  orc_q y, wfc, xt;   /* measurement vector, fully connected weights, proxy x~ */
+  orc_q w[8];         /* conv weights of layer l */
+  orc_q a[8];         /* output of conv layer l (after the ReLU) */
+  int acc_fp32;       /* error model only: sums are accumulated in FP32 */
+} orc_quant;
+
+/* v rounded into format fmt (no scale). */
+double orc_round(double v, int fmt);
+/* out[i] = round(x[i] / scale) * scale. */
+void orc_quantize(const double *x, double *out, long n, int fmt, double scale);
+/* The forward map with every operand rounded where qs says, sums exact: y, W_fc and
+ * the conv weights are rounded before use, x~ and each layer's output after it is
+ * computed.  With every point ORC_Q_NONE it is orc_forward.  sigma (nullable) [B][N]
+ * receives a model of the standard deviation of each output pixel's error against
+ * the exact forward map: every rounding is an independent error, uniform over one
+ * spacing of its format, propagated through the layers to first order; with
+ * acc_fp32 the rounding of FP32 running sums is added. */
+void orc_forward_q(const orc_net *net, const double *wfc, const double *const *w,
+                   const double *const *b, const double *y, int B, const orc_quant *qs,
+                   double *xhat, double *sigma);
+
 /* L = (1/B) sum_b ||xhat_b - x_b||^2; g (nullable) = dL/dxhat = (2/B)(xhat - x). */
 double orc_loss(const double *xhat, const double *x, int B, int N, double *g);
 

@@ -36,6 +36,20 @@ MUTANTS = {
                     "const double s = ne > 0.0 ? sqrt(ny / ne) * pow(10.0, -snr_db / 10.0) : 0.0;"),
     "dct_sign": ("C[(long)k * n + i] = a * cos(pi * (2 * i + 1) * k / (2.0 * n));",
                  "C[(long)k * n + i] = a * cos(pi * (2 * i - 1) * k / (2.0 * n));"),
+    "round_ties_away": ("if (d > 0.5 || (d == 0.5 && fmod(fl, 2.0) != 0.0)) fl += 1.0;", "if (d >= 0.5) fl += 1.0;"),
+    "round_no_subnormals": ("int E = e - 1 < emin ? emin : e - 1;\n  double q = ldexp(1.0, E - p + 1);",
+                            "int E = e - 1;\n  double q = ldexp(1.0, E - p + 1);"),
+    "e4m3_max": ("return round_format(v, 4, -6, 448.0, 1);", "return round_format(v, 4, -6, 480.0, 1);"),
+    "bf16_bits": ("return round_format(v, 8, -126, BF16_MAX, 0);", "return round_format(v, 7, -126, BF16_MAX, 0);"),
+    "proxy_not_rounded": ("double v = q_value(a[0][p], qs->xt);", "double v = a[0][p];"),
+    "hidden_not_rounded": ("double v = q_value(a[l + 1][i], qs->a[l]);", "double v = a[l + 1][i];"),
+    "y_not_rounded": ("for (int m = 0; m < M; ++m) yq[m] = q_value(yb[m], qs->y);",
+                      "for (int m = 0; m < M; ++m) yq[m] = yb[m];"),
+    "errmodel_weight_term": ("wc[i] = wv[l][i] + ca * w2[i];", "wc[i] = ca * w2[i];"),
+    "errmodel_relu_mask": ("Vn[i] = (relu && !(a[l + 1][i] > 0.0)) ? 0.0 : t1[i] + t2[i];",
+                           "Vn[i] = t1[i] + t2[i];"),
+    "errmodel_acc_coeff": ("return acc_fp32 ? (double)n / 24.0 * ldexp(1.0, -46) : 0.0;",
+                           "return acc_fp32 ? (double)n / 24.0 * ldexp(1.0, -48) : 0.0;"),
 }
 
 
@@ -56,7 +70,8 @@ def _pins_fail(so):
     env = dict(os.environ, ORC_LIB_PATH=so, OMP_NUM_THREADS="2")
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
                         os.path.join(ROOT, "tests", "test_oracle_pins.py"),
-                        os.path.join(ROOT, "tests", "test_oracle_grad.py")],
+                        os.path.join(ROOT, "tests", "test_oracle_grad.py"),
+                        os.path.join(ROOT, "tests", "test_oracle_quant.py")],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     return r.returncode != 0, r.stdout[-400:]
 
