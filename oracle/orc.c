@@ -202,9 +202,12 @@ static double acc_var_coeff(int acc_fp32, long n) {
  * of each output pixel's error against the exact network, propagated linearly:
  * a rounding error passes through a layer like a small input change (weights
  * squared, ReLU passing it where the unit is active), and errors are taken as
- * independent with the variances of q_var and acc_var_coeff. */
-static void forward_one_q(const orc_net *net, const double *wfcq, const double *wfcv,
-                          const double *const *wq, const double *const *wv, const double *const *b,
+ * independent with the variances of q_var and acc_var_coeff.  wfc2, w2[l] hold the
+ * squared rounded weights and wfcc, wc[l] the per-product variances of the weight
+ * rounding plus the accumulation step (both read only when var != NULL). */
+static void forward_one_q(const orc_net *net, const double *wfcq, const double *wfc2,
+                          const double *wfcc, const double *const *wq, const double *const *w2,
+                          const double *const *wc, const double *const *b,
                           const double *yb, const orc_quant *qs, double *act, double *var) {
   const int N = net->n1 * net->n2, M = net->M, n1 = net->n1, n2 = net->n2;
   double *a[9], *z[8];
@@ -224,15 +227,11 @@ static void forward_one_q(const orc_net *net, const double *wfcq, const double *
     zero = (double *)calloc((size_t)cmax, sizeof(double));
     /* proxy: rounding of y (through W^2), of W_fc (times y^2), of the sum, of x~ */
     double *vy = (double *)malloc(sizeof(double) * M), *y2 = (double *)malloc(sizeof(double) * M);
-    double *w2 = (double *)malloc(sizeof(double) * (long)N * M);
-    double *wc = (double *)malloc(sizeof(double) * (long)N * M);
-    const double ca = acc_var_coeff(qs->acc_fp32, M);
     for (int m = 0; m < M; ++m) { vy[m] = q_var(yb[m], qs->y); y2[m] = yq[m] * yq[m]; }
-    for (long i = 0; i < (long)N * M; ++i) { w2[i] = wfcq[i] * wfcq[i]; wc[i] = wfcv[i] + ca * w2[i]; }
-    orc_proxy(w2, vy, t1, 1, M, N);
-    orc_proxy(wc, y2, t2, 1, M, N);
+    orc_proxy(wfc2, vy, t1, 1, M, N);
+    orc_proxy(wfcc, y2, t2, 1, M, N);
     for (int p = 0; p < N; ++p) V[p] = t1[p] + t2[p];
-    free(vy); free(y2); free(w2); free(wc);
+    free(vy); free(y2);
   }
   for (int p = 0; p < N; ++p) {
     double v = q_value(a[0][p], qs->xt);
@@ -242,18 +241,14 @@ static void forward_one_q(const orc_net *net, const double *wfcq, const double *
   for (int l = 0; l < net->L; ++l) {
     const int relu = (l < net->L - 1) || net->relu_last;
     const int Cin = net->C[l], Cout = net->C[l + 1], k = net->k[l];
-    const long nw = (long)Cout * Cin * k * k, no = (long)Cout * N;
+    const long no = (long)Cout * N;
     orc_conv_layer(a[l], Cin, n1, n2, wq[l], Cout, k, b[l], net->bias_full, relu, z[l], a[l + 1]);
     if (var) {
       /* Vz = W^2 * V + (var(W) + c W^2) * a^2 */
-      double *w2 = (double *)malloc(sizeof(double) * nw), *wc = (double *)malloc(sizeof(double) * nw);
-      const double ca = acc_var_coeff(qs->acc_fp32, (long)Cin * k * k + 1);
-      for (long i = 0; i < nw; ++i) { w2[i] = wq[l][i] * wq[l][i]; wc[i] = wv[l][i] + ca * w2[i]; }
       for (long i = 0; i < (long)Cin * N; ++i) sq[i] = a[l][i] * a[l][i];
-      orc_conv_layer(V, Cin, n1, n2, w2, Cout, k, zero, 0, 0, NULL, t1);
-      orc_conv_layer(sq, Cin, n1, n2, wc, Cout, k, zero, 0, 0, NULL, t2);
+      orc_conv_layer(V, Cin, n1, n2, w2[l], Cout, k, zero, 0, 0, NULL, t1);
+      orc_conv_layer(sq, Cin, n1, n2, wc[l], Cout, k, zero, 0, 0, NULL, t2);
       for (long i = 0; i < no; ++i) Vn[i] = (relu && !(a[l + 1][i] > 0.0)) ? 0.0 : t1[i] + t2[i];
-      free(w2); free(wc);
     }
     for (long i = 0; i < no; ++i) {
       double v = q_value(a[l + 1][i], qs->a[l]);
@@ -274,23 +269,36 @@ void orc_forward_q(const orc_net *net, const double *wfc, const double *const *w
                    double *xhat, double *sigma) {
   const int N = net->n1 * net->n2, M = net->M, L = net->L;
   const long per = orc_acts_per_image(net);
-  /* rounded weights and (for the error model) their rounding-error variances */
-  double *wfcq = (double *)malloc(sizeof(double) * (long)N * M);
-  double *wfcv = (double *)malloc(sizeof(double) * (long)N * M);
-  for (long i = 0; i < (long)N * M; ++i) { wfcq[i] = q_value(wfc[i], qs->wfc); wfcv[i] = q_var(wfc[i], qs->wfc); }
-  double *wq[8], *wv[8];
+  /* rounded weights and, for the error model, their squares W^2 and the variances
+   * var(W) + c W^2 of each product's weight rounding and accumulation step (c from
+   * acc_var_coeff for the layer's number of terms) */
+  const long nfc = (long)N * M;
+  double *wfcq = (double *)malloc(sizeof(double) * nfc);
+  double *wfc2 = sigma ? (double *)malloc(sizeof(double) * nfc) : NULL;
+  double *wfcc = sigma ? (double *)malloc(sizeof(double) * nfc) : NULL;
+  const double cfc = acc_var_coeff(qs->acc_fp32, M);
+  for (long i = 0; i < nfc; ++i) {
+    wfcq[i] = q_value(wfc[i], qs->wfc);
+    if (sigma) { wfc2[i] = wfcq[i] * wfcq[i]; wfcc[i] = q_var(wfc[i], qs->wfc) + cfc * wfc2[i]; }
+  }
+  double *wq[8], *w2[8], *wc[8];
   for (int l = 0; l < L; ++l) {
     const long nw = (long)net->C[l + 1] * net->C[l] * net->k[l] * net->k[l];
+    const double ca = acc_var_coeff(qs->acc_fp32, (long)net->C[l] * net->k[l] * net->k[l] + 1);
     wq[l] = (double *)malloc(sizeof(double) * nw);
-    wv[l] = (double *)malloc(sizeof(double) * nw);
-    for (long i = 0; i < nw; ++i) { wq[l][i] = q_value(w[l][i], qs->w[l]); wv[l][i] = q_var(w[l][i], qs->w[l]); }
+    w2[l] = sigma ? (double *)malloc(sizeof(double) * nw) : NULL;
+    wc[l] = sigma ? (double *)malloc(sizeof(double) * nw) : NULL;
+    for (long i = 0; i < nw; ++i) {
+      wq[l][i] = q_value(w[l][i], qs->w[l]);
+      if (sigma) { w2[l][i] = wq[l][i] * wq[l][i]; wc[l][i] = q_var(w[l][i], qs->w[l]) + ca * w2[l][i]; }
+    }
   }
 #pragma omp parallel for schedule(dynamic, 1)
   for (int bi = 0; bi < B; ++bi) {
     double *act = (double *)malloc(sizeof(double) * per);
     double *var = sigma ? (double *)malloc(sizeof(double) * N) : NULL;
-    forward_one_q(net, wfcq, wfcv, (const double *const *)wq, (const double *const *)wv, b,
-                  y + (long)bi * M, qs, act, var);
+    forward_one_q(net, wfcq, wfc2, wfcc, (const double *const *)wq, (const double *const *)w2,
+                  (const double *const *)wc, b, y + (long)bi * M, qs, act, var);
     double *a[9], *z[8];
     acts_layout(net, act, a, z);
     memcpy(xhat + (long)bi * N, a[L], sizeof(double) * N);
@@ -299,9 +307,10 @@ void orc_forward_q(const orc_net *net, const double *wfc, const double *const *w
     free(var);
     free(act);
   }
-  for (int l = 0; l < L; ++l) { free(wq[l]); free(wv[l]); }
+  for (int l = 0; l < L; ++l) { free(wq[l]); free(w2[l]); free(wc[l]); }
   free(wfcq);
-  free(wfcv);
+  free(wfc2);
+  free(wfcc);
 }
 
 /* ------------------------------------------------------------- Sec. 4 loss */

@@ -45,7 +45,7 @@ MUTANTS = {
     "hidden_not_rounded": ("double v = q_value(a[l + 1][i], qs->a[l]);", "double v = a[l + 1][i];"),
     "y_not_rounded": ("for (int m = 0; m < M; ++m) yq[m] = q_value(yb[m], qs->y);",
                       "for (int m = 0; m < M; ++m) yq[m] = yb[m];"),
-    "errmodel_weight_term": ("wc[i] = wv[l][i] + ca * w2[i];", "wc[i] = ca * w2[i];"),
+    "errmodel_weight_term": ("wc[l][i] = q_var(w[l][i], qs->w[l]) + ca * w2[l][i];", "wc[l][i] = ca * w2[l][i];"),
     "errmodel_relu_mask": ("Vn[i] = (relu && !(a[l + 1][i] > 0.0)) ? 0.0 : t1[i] + t2[i];",
                            "Vn[i] = t1[i] + t2[i];"),
     "errmodel_acc_coeff": ("return acc_fp32 ? (double)n / 24.0 * ldexp(1.0, -46) : 0.0;",
