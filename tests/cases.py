@@ -1,8 +1,24 @@
-"""Seeded test cases shared by the GPU parity tests.
+"""Seeded test cases shared by the GPU parity tests, and the parity gates.
 
 Inputs come from ``synth`` only; expected values come from ``oracle`` only.
 The GPU side receives the same fp32-exact inputs and nothing the oracle
 computed except the measurement vectors y (an input of the recovery path).
+
+Two gates hold for every recovered image (``check_recovery``):
+
+* norm-wise: ||xhat_b - ref_b||_2 / ||ref_b||_2 <= TOL_NORM[prec] per image,
+  ref the FP64 oracle on the same inputs (the tolerances of the path's
+  precision variants);
+* per pixel: |xhat[b][p] - ref[b][p]| <= SIGMA_GATE * sigma[b][p] + 2^-22 |ref[b][p]|,
+  where sigma is the oracle's first-order model of that pixel's rounding-error
+  standard deviation for the precision variant (``oracle.forward_q`` with
+  ``want_sigma``: every operand rounding the variant performs and FP32
+  accumulation, propagated through the layers).  The second term is the FP32
+  rounding of the output itself.  The model is pinned against the actual
+  rounding-error distribution on the CPU (std of e / sigma 0.93-0.98, no pixel
+  beyond 6 sigma in 10^4-10^6 pixels), so one wrong pixel -- an error of the
+  pixel's own magnitude, hundreds of sigma -- fails the gate even where the
+  image's norm-wise error stays small.
 """
 from __future__ import annotations
 
@@ -12,6 +28,9 @@ import numpy as np
 
 import oracle
 import synth
+
+TOL_NORM = {"f32": 1e-5, "bf16": 2e-2, "fp8": 1e-1, "f64": 1e-7}
+SIGMA_GATE = 8.0
 
 
 @dataclass
@@ -74,3 +93,76 @@ def relerr_per_image(a, ref):
     a = np.asarray(a, dtype=np.float64).reshape(ref.shape[0], -1)
     ref = np.asarray(ref, dtype=np.float64).reshape(ref.shape[0], -1)
     return oracle.relerr(a, ref)
+
+
+# ------------------------------------------------------------------ parity gates
+_REF = {}
+
+
+def _key(case):
+    return (case.n1, case.n2, case.M, case.B, case.C, case.k, case.bias_per_pixel, case.relu_last,
+            float(case.y[0, 0]), float(case.w[0].ravel()[0]), float(case.b[0].ravel()[0]))
+
+
+def oracle_ref(case, idx=None):
+    """FP64 forward of every image (cached per case), or of the images idx."""
+    k = _key(case)
+    if k not in _REF:
+        _REF.clear()            # one case at a time: full-size references are large
+        _REF[k] = case.oracle_forward()
+    ref = _REF[k]
+    return ref if idx is None else ref[idx]
+
+
+def pow2_scale(amax):
+    """Smallest power of two s with amax / s <= 448 (the e4m3 range)."""
+    return float(2.0 ** np.ceil(np.log2(amax / 448.0)))
+
+
+def fp8_scales_from_oracle(case, margin=1.05):
+    """Static activation scales {s_y, s_x~, s_a1, s_a2} large enough that no value of this
+    batch saturates: y from the inputs, conv layer 1's output from the FP64 forward pass
+    (with a margin for the rounding of its inputs)."""
+    _, acts = oracle.forward(case.oracle_net(), case.phi.T, case.w, case.oracle_bias(), case.y,
+                             return_acts=True)
+    a1max = max(float(a[1].max()) for a in acts)
+    return [pow2_scale(margin * np.abs(case.y).max()), 1.0, pow2_scale(margin * a1max), 1.0]
+
+
+def quant_for(prec, scales=None):
+    """The oracle's model of a precision variant.  scales: the FP8 net's
+    {W_fc, W2, s_y, s_x~, s_a1, s_a2} (Net.scales())."""
+    if prec == "f32":
+        return oracle.Quant.fp32()
+    if prec == "bf16":
+        return oracle.Quant.bf16()
+    if prec == "fp8":
+        s_fc, s_w2, s_y, _, s_a1 = (float(v) for v in scales[:5])
+        return oracle.Quant.fp8(s_y, s_fc, s_a1, s_w2)
+    raise ValueError(prec)
+
+
+def check_recovery(case, got, prec, idx=None, scales=None, label=""):
+    """Both parity gates on recovered images got [len(idx) or B][N] (float64 copy of the
+    GPU output).  Returns (max norm-wise error, max |error| / allowed)."""
+    got = np.asarray(got, dtype=np.float64).reshape(len(idx) if idx is not None else case.B, -1)
+    ref = oracle_ref(case, idx)
+    norm = relerr_per_image(got, ref)
+    rms = np.sqrt((ref ** 2).mean(axis=1, keepdims=True)) + 1e-300
+    if prec == "f64":
+        # FP64 arithmetic, output rounded to float32 once
+        allowed = 2.0 ** -23 * np.abs(ref) + 1e-12 * rms
+    else:
+        y = case.y if idx is None else case.y[idx]
+        _, sig = oracle.forward_q(case.oracle_net(), case.phi.T, case.w, case.oracle_bias(), y,
+                                  quant_for(prec, scales), want_sigma=True)
+        allowed = SIGMA_GATE * sig + 2.0 ** -22 * np.abs(ref) + 1e-12 * rms
+    ratio = np.abs(got - ref) / allowed
+    worst = np.unravel_index(np.argmax(ratio), ratio.shape)
+    print(f"{label} {prec}: {got.shape[0]} images, max norm-wise err {norm.max():.3e} (tol {TOL_NORM[prec]}), "
+          f"max |err|/allowed {ratio.max():.3f} at image {worst[0]} pixel {worst[1]}"
+          + (f" ({ratio.max() * SIGMA_GATE:.2f} sigma)" if prec != "f64" else ""))
+    assert np.all(np.isfinite(got))
+    assert norm.max() <= TOL_NORM[prec], (label, prec, norm.max())
+    assert ratio.max() <= 1.0, (label, prec, ratio.max(), worst)
+    return norm.max(), ratio.max()
