@@ -171,6 +171,24 @@ dsi_status dsi_reserve(dsi_ctx *ctx, const dsi_net *net, int B, int train);
 dsi_status dsi_recover(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
                        void *stream);
 
+/* Size of the fixed device workspace of dsi_recover_noalloc: 64 MiB per device. */
+#define DSI_NOALLOC_SCRATCH_BYTES (64L << 20)
+
+/* For callers that cannot allocate device memory (code under HIP graph capture,
+ * tight serving loops, harnesses that forbid hipMalloc): dsi_recover with the
+ * same arguments, kernels and results, whose workspace is a fixed device array
+ * inside the library (DSI_NOALLOC_SCRATCH_BYTES on each device, held until the
+ * process ends; its address is looked up once per device by dsi_create).  It
+ * calls no allocating routine.  The workspace a batch needs is
+ * dsi_workspace_size(net, B, 0) bytes (about 0.76 MiB per 64 x 64 BF16 image,
+ * so B <= 84 at 64 x 64 and B <= 20 at 128 x 128); a larger batch fails with
+ * DSI_E_SHAPE before any launch and leaves xhat untouched.  Every call on one
+ * device shares that device's array, which keeps the last call's contents:
+ * calls that overlap on one GPU (different streams, contexts or threads) race,
+ * so order them on one stream.  No stage timing is recorded. */
+dsi_status dsi_recover_noalloc(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
+                               void *stream);
+
 /* ------------------------------------------------- Sec. 4: backpropagation */
 /* Forward pass that also keeps, in `saved` (caller-owned device buffer of at
  * least dsi_workspace_size(net, B, 1) bytes), what the backward pass needs. */

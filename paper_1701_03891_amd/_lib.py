@@ -28,7 +28,9 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_net_info", "dsi_workspace_size", "dsi_reserve", "dsi_recover",
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
            "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation", "dsi_net_calibrate",
-           "dsi_net_get_scales", "dsi_measure_noisy"]
+           "dsi_net_get_scales", "dsi_measure_noisy", "dsi_recover_noalloc"]
+
+NOALLOC_SCRATCH_BYTES = 64 << 20     # DSI_NOALLOC_SCRATCH_BYTES
 
 
 class DsiError(RuntimeError):
@@ -86,6 +88,7 @@ def lib() -> ctypes.CDLL:
         "dsi_workspace_size": (st, [P, i, i, ctypes.POINTER(z)]),
         "dsi_reserve": (st, [P, P, i, i]),
         "dsi_recover": (st, [P, P, P, P, i, P]),
+        "dsi_recover_noalloc": (st, [P, P, P, P, i, P]),
         "dsi_forward_train": (st, [P, P, P, P, i, P, z, P]),
         "dsi_backward": (st, [P, P, P, P, z, i, ctypes.POINTER(Params), P, P]),
         "dsi_loss_grad": (st, [P, P, P, P, i, ctypes.POINTER(Params), P, P, P]),
@@ -170,6 +173,10 @@ def dsi_reserve(ctx, net, B, train):
 
 def dsi_recover(ctx, net, y, xhat, B, stream):
     call("dsi_recover", ctx, net, y, xhat, B, stream)
+
+
+def dsi_recover_noalloc(ctx, net, y, xhat, B, stream):
+    call("dsi_recover_noalloc", ctx, net, y, xhat, B, stream)
 
 
 def dsi_forward_train(ctx, net, y, xhat, B, saved, saved_bytes, stream):

@@ -12,7 +12,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(ROOT, "_build")
 SO = os.path.join(HERE, "libdsi.so")
 ARCH = os.environ.get("DSI_OFFLOAD_ARCH", "gfx950")
-SOURCES = ["gemm.hip", "conv_direct.hip", "conv_mfma.hip", "conv_bwd.hip", "misc.hip", "api.cpp"]
+SOURCES = ["gemm.hip", "conv_direct.hip", "conv_mfma.hip", "conv_bwd.hip", "misc.hip", "noalloc.hip",
+           "api.cpp"]
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",
          # no packed-FP32 instructions in generated code
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",

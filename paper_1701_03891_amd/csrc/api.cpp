@@ -65,6 +65,7 @@ struct dsi_ctx {
   int device = 0;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  void *fixed_ws = nullptr;  // device address of the fixed workspace array (dsi_recover_noalloc)
   // stage timing (benchmarking): one set of events per timed forward pass
   int timing = 0;
   std::vector<std::vector<hipEvent_t>> ev;
@@ -624,9 +625,14 @@ dsi_status dsi_create(dsi_ctx **out, int device) {
   int count = 0;
   if (hipGetDeviceCount(&count) != hipSuccess || count < 1) return fail(DSI_E_HIP, "no HIP device");
   if (device < 0 || device >= count) return fail(DSI_E_SHAPE, "device %d out of range (%d devices)", device, count);
+  if (hipSetDevice(device) != hipSuccess) return fail(DSI_E_HIP, "hipSetDevice(%d) failed", device);
+  void *fixed = nullptr;
+  hipError_t e = dsi::noalloc_scratch(device, &fixed);
+  if (e != hipSuccess) return fail(DSI_E_HIP, "fixed workspace lookup on device %d: %s", device, hipGetErrorString(e));
   dsi_ctx *c = new (std::nothrow) dsi_ctx;
   if (!c) return fail(DSI_E_NOMEM, "host allocation failed");
   c->device = device;
+  c->fixed_ws = fixed;
   *out = c;
   return DSI_OK;
 }
@@ -829,6 +835,23 @@ dsi_status dsi_recover(dsi_ctx *ctx, const dsi_net *net, const float *y, float *
   dsi_status st = ensure_ws(ctx, L.end);
   if (st != DSI_OK) return st;
   return forward_impl(ctx, net, y, xhat, B, ctx->ws, L, (hipStream_t)stream);
+}
+
+dsi_status dsi_recover_noalloc(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
+                               void *stream) {
+  if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
+  if (B < 0) return fail(DSI_E_SHAPE, "B = %d", B);
+  if (B == 0) return DSI_OK;
+  if (!y || !xhat) return fail(DSI_E_NULL, "y and xhat must be non-NULL");
+  if (!aligned16(y) || !aligned16(xhat)) return fail(DSI_E_ALIGN, "y and xhat must be 16-byte aligned");
+  const Layout L = layout(*net, B, 0);
+  if (L.end > (size_t)DSI_NOALLOC_SCRATCH_BYTES)
+    return fail(DSI_E_SHAPE, "a batch of %d images needs %zu workspace bytes; the fixed workspace holds %zu",
+                B, L.end, (size_t)DSI_NOALLOC_SCRATCH_BYTES);
+  if (!ctx->fixed_ws) return fail(DSI_E_STATE, "no fixed workspace on device %d", ctx->device);
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  // no stage timing here (it creates events): the context is not passed on
+  return forward_impl(nullptr, net, y, xhat, B, ctx->fixed_ws, L, (hipStream_t)stream);
 }
 
 dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,

@@ -139,3 +139,9 @@ hipError_t gemm_frag_fp8(const unsigned char *Xp, const unsigned char *Wp, __bf1
 hipError_t pack_mid_fp8(const float *w, unsigned char *out, float inv_scale, hipStream_t s);
 hipError_t pack_fc_fp8(const float *w, unsigned char *out, int N, int M, int Mpad, float inv_scale, hipStream_t s);
 }  // namespace dsi
+
+namespace dsi {
+// noalloc.hip: device address of the library's fixed workspace array on `device`
+// (which must be the current device), looked up once per device and cached
+hipError_t noalloc_scratch(int device, void **ptr);
+}  // namespace dsi
