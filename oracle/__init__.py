@@ -71,6 +71,7 @@ def lib():
             "orc_dct_matrix": (None, [i, P]),
             "orc_spectral_norm": (d, [P, i, i, i]),
             "orc_ista_dct": (i, [P, P, i, i, i, i, i, d, P, P]),
+            "orc_ista_dct_batch": (None, [P, P, i, i, i, i, i, i, d, P, P, P]),
             "orc_round": (d, [d, i]),
             "orc_quantize": (None, [P, P, l_, i, d]),
             "orc_forward_q": (None, [P, P, P, P, P, i, P, P, P]),
@@ -444,3 +445,17 @@ def ista_dct(phi, y, n1, n2, stages=12, iters=300, decay=0.3):
     x = np.empty(n1 * n2)
     ns = lib().orc_ista_dct(_p(phi), _p(y), M, n1, n2, stages, iters, decay, _p(s), _p(x))
     return x, s.reshape(n1, n2), ns
+
+
+def ista_dct_batch(phi, Y, n1, n2, stages=12, iters=300, decay=0.3):
+    """ista_dct on every row of Y [B][M] (same steps and sums per image; the passes
+    over Phi are shared).  Returns X [B][N], S [B][n1][n2], support sizes [B]."""
+    phi, Y = _c(phi), _c(np.atleast_2d(Y))
+    B, M = Y.shape
+    N = n1 * n2
+    S = np.empty((B, N))
+    X = np.empty((B, N))
+    ns = np.zeros(B, dtype=np.int32)
+    lib().orc_ista_dct_batch(_p(phi), _p(Y), B, M, n1, n2, stages, iters, decay, _p(S), _p(X),
+                             ns.ctypes.data_as(ctypes.c_void_p))
+    return X, S.reshape(B, n1, n2), ns

@@ -666,53 +666,13 @@ static int chol_solve(double *G, double *h, int n) {
   return 0;
 }
 
-int orc_ista_dct(const double *phi, const double *y, int M, int n1, int n2, int stages,
-                 int iters, double decay, double *s, double *x) {
+/* Least-squares debias of one ISTA result on its support {|s_j| > 1e-6 max|s|}
+ * (in place on s, when the support has at most M elements and its Gram matrix is
+ * positive definite), then the image x = Psi s.  Returns the support size. */
+static int ista_debias(const double *phi, const double *y, int M, int n1, int n2, const double *C1,
+                       const double *C2, double *s, double *x) {
   const int N = n1 * n2;
-  double *C1 = (double *)malloc(sizeof(double) * n1 * n1);
-  double *C2 = (double *)malloc(sizeof(double) * n2 * n2);
-  orc_dct_matrix(n1, C1);
-  orc_dct_matrix(n2, C2);
   double *img = (double *)malloc(sizeof(double) * N), *tmp = (double *)malloc(sizeof(double) * N);
-  double *res = (double *)malloc(sizeof(double) * M), *grad = (double *)malloc(sizeof(double) * N);
-  double *back = (double *)calloc((size_t)N, sizeof(double));
-  /* A = Phi Psi has the same spectral norm as Phi (Psi orthonormal) */
-  double sig = orc_spectral_norm(phi, M, N, 300);
-  double tau = 0.99 / (sig * sig);
-  /* lam_0 = 0.5 ||A^T y||_inf */
-  for (int n = 0; n < N; ++n) {
-    double acc = 0.0;
-    for (int m = 0; m < M; ++m) acc += phi[(long)m * N + n] * y[m];
-    back[n] = acc;
-  }
-  dct2(C1, C2, n1, n2, back, grad, tmp);
-  double lam = 0.0;
-  for (int n = 0; n < N; ++n) lam = fabs(grad[n]) > lam ? fabs(grad[n]) : lam;
-  lam *= 0.5;
-  memset(s, 0, sizeof(double) * N);
-  for (int st = 0; st < stages; ++st) {
-    for (int it = 0; it < iters; ++it) {
-      idct2(C1, C2, n1, n2, s, img, tmp);             /* image of the current coefficients */
-      for (int m = 0; m < M; ++m) {                    /* r = y - A s */
-        double acc = 0.0;
-        for (int n = 0; n < N; ++n) acc += phi[(long)m * N + n] * img[n];
-        res[m] = y[m] - acc;
-      }
-      for (int n = 0; n < N; ++n) {                    /* A^T r */
-        double acc = 0.0;
-        for (int m = 0; m < M; ++m) acc += phi[(long)m * N + n] * res[m];
-        back[n] = acc;
-      }
-      dct2(C1, C2, n1, n2, back, grad, tmp);
-      const double thr = lam * tau;
-      for (int n = 0; n < N; ++n) {                    /* soft thresholding */
-        double v = s[n] + tau * grad[n];
-        s[n] = v > thr ? v - thr : (v < -thr ? v + thr : 0.0);
-      }
-    }
-    lam *= decay;
-  }
-  /* debias: least squares on the detected support */
   double smax = 0.0;
   for (int n = 0; n < N; ++n) smax = fabs(s[n]) > smax ? fabs(s[n]) : smax;
   int *sup = (int *)malloc(sizeof(int) * N);
@@ -751,6 +711,108 @@ int orc_ista_dct(const double *phi, const double *y, int M, int n1, int n2, int 
     free(AS); free(G); free(h); free(e);
   }
   idct2(C1, C2, n1, n2, s, x, tmp);
-  free(sup); free(C1); free(C2); free(img); free(tmp); free(res); free(grad); free(back);
+  free(sup); free(img); free(tmp);
+  return ns;
+}
+
+/* ISTA on B measurement vectors at once.  Every image goes through exactly the
+ * steps (and the order of every sum) of a single-image run; the images share only
+ * the passes over Phi: the residual r_b = y_b - Phi Psi s_b and the back-projection
+ * Phi^T r_b are computed for all b while a row of Phi is at hand, each sum still
+ * over ascending m or n.  Y [B][M]; S, X [B][n1 n2]; supp [B] (nullable) receives
+ * the debias support sizes. */
+void orc_ista_dct_batch(const double *phi, const double *Y, int B, int M, int n1, int n2, int stages,
+                        int iters, double decay, double *S, double *X, int *supp) {
+  const int N = n1 * n2;
+  const int NB = 64;                                    /* columns of Phi per thread block */
+  double *C1 = (double *)malloc(sizeof(double) * n1 * n1);
+  double *C2 = (double *)malloc(sizeof(double) * n2 * n2);
+  orc_dct_matrix(n1, C1);
+  orc_dct_matrix(n2, C2);
+  double *imgT = (double *)malloc(sizeof(double) * (long)N * B);   /* [N][B] */
+  double *backT = (double *)malloc(sizeof(double) * (long)N * B);  /* [N][B] */
+  double *resT = (double *)malloc(sizeof(double) * (long)M * B);   /* [M][B] */
+  double *work = (double *)malloc(sizeof(double) * (long)3 * N * B);  /* per image: img, grad, tmp */
+  double *lam = (double *)malloc(sizeof(double) * B);
+  /* A = Phi Psi has the same spectral norm as Phi (Psi orthonormal) */
+  const double sig = orc_spectral_norm(phi, M, N, 300);
+  const double tau = 0.99 / (sig * sig);
+  /* back-projection Phi^T v for every image: backT[n][b] = sum over ascending m */
+#define ISTA_BACK(V)                                                                   \
+  do {                                                                                 \
+    _Pragma("omp parallel for schedule(static)")                                      \
+    for (int n0 = 0; n0 < N; n0 += NB) {                                               \
+      const int n1e = n0 + NB < N ? n0 + NB : N;                                       \
+      for (long q = (long)n0 * B; q < (long)n1e * B; ++q) backT[q] = 0.0;              \
+      for (int m = 0; m < M; ++m)                                                      \
+        for (int n = n0; n < n1e; ++n) {                                               \
+          const double f = phi[(long)m * N + n];                                       \
+          for (int b = 0; b < B; ++b) backT[(long)n * B + b] += f * (V);               \
+        }                                                                              \
+    }                                                                                  \
+  } while (0)
+  /* lam_0 = 0.5 ||A^T y||_inf per image */
+  ISTA_BACK(Y[(long)b * M + m]);
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int b = 0; b < B; ++b) {
+    double *img = work + (long)b * 3 * N, *grad = img + N, *tmp = grad + N;
+    for (int n = 0; n < N; ++n) img[n] = backT[(long)n * B + b];
+    dct2(C1, C2, n1, n2, img, grad, tmp);
+    double l = 0.0;
+    for (int n = 0; n < N; ++n) l = fabs(grad[n]) > l ? fabs(grad[n]) : l;
+    lam[b] = 0.5 * l;
+  }
+  memset(S, 0, sizeof(double) * (long)N * B);
+  for (int st = 0; st < stages; ++st) {
+    for (int it = 0; it < iters; ++it) {
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int b = 0; b < B; ++b) {                      /* image of the current coefficients */
+        double *img = work + (long)b * 3 * N, *tmp = img + 2 * N;
+        idct2(C1, C2, n1, n2, S + (long)b * N, img, tmp);
+        for (int n = 0; n < N; ++n) imgT[(long)n * B + b] = img[n];
+      }
+#pragma omp parallel for schedule(static)
+      for (int m = 0; m < M; ++m) {                      /* r = y - A s */
+        double acc[256];
+        for (int b0 = 0; b0 < B; b0 += 256) {
+          const int bn = B - b0 < 256 ? B - b0 : 256;
+          for (int b = 0; b < bn; ++b) acc[b] = 0.0;
+          for (int n = 0; n < N; ++n) {
+            const double f = phi[(long)m * N + n];
+            const double *im = imgT + (long)n * B + b0;
+            for (int b = 0; b < bn; ++b) acc[b] += f * im[b];
+          }
+          for (int b = 0; b < bn; ++b) resT[(long)m * B + b0 + b] = Y[(long)(b0 + b) * M + m] - acc[b];
+        }
+      }
+      ISTA_BACK(resT[(long)m * B + b]);                  /* A^T r (before the DCT) */
+#pragma omp parallel for schedule(dynamic, 1)
+      for (int b = 0; b < B; ++b) {
+        double *img = work + (long)b * 3 * N, *grad = img + N, *tmp = grad + N;
+        double *s = S + (long)b * N;
+        for (int n = 0; n < N; ++n) img[n] = backT[(long)n * B + b];
+        dct2(C1, C2, n1, n2, img, grad, tmp);
+        const double thr = lam[b] * tau;
+        for (int n = 0; n < N; ++n) {                    /* soft thresholding */
+          double v = s[n] + tau * grad[n];
+          s[n] = v > thr ? v - thr : (v < -thr ? v + thr : 0.0);
+        }
+      }
+    }
+    for (int b = 0; b < B; ++b) lam[b] *= decay;
+  }
+#undef ISTA_BACK
+#pragma omp parallel for schedule(dynamic, 1)
+  for (int b = 0; b < B; ++b) {
+    int ns = ista_debias(phi, Y + (long)b * M, M, n1, n2, C1, C2, S + (long)b * N, X + (long)b * N);
+    if (supp) supp[b] = ns;
+  }
+  free(C1); free(C2); free(imgT); free(backT); free(resT); free(work); free(lam);
+}
+
+int orc_ista_dct(const double *phi, const double *y, int M, int n1, int n2, int stages,
+                 int iters, double decay, double *s, double *x) {
+  int ns = 0;
+  orc_ista_dct_batch(phi, y, 1, M, n1, n2, stages, iters, decay, s, x, &ns);
   return ns;
 }

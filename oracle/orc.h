@@ -146,6 +146,11 @@ double orc_spectral_norm(const double *phi, int M, int N, int iters);
  * [n1][n2] and the image [n1][n2].  Returns the support size. */
 int orc_ista_dct(const double *phi, const double *y, int M, int n1, int n2, int stages,
                  int iters, double decay, double *s, double *x);
+/* orc_ista_dct on B measurement vectors Y [B][M] at once (each image through the
+ * same steps and sums as a single run; the passes over Phi are shared).  S, X
+ * [B][n1 n2]; supp [B] (nullable) receives the support sizes. */
+void orc_ista_dct_batch(const double *phi, const double *Y, int B, int M, int n1, int n2, int stages,
+                        int iters, double decay, double *S, double *X, int *supp);
 
 #ifdef __cplusplus
 }

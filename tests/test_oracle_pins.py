@@ -321,6 +321,30 @@ def test_p17_ista_recovers_sparse_exactly_32(orc):
     assert np.linalg.norm(xr - x.reshape(-1)) / np.linalg.norm(x) < 1e-9
 
 
+def test_p17_ista_batch_recovers_each_sparse_signal_and_is_batch_independent(orc):
+    """The batched ISTA (several measurement vectors in one call, sharing the passes over
+    Phi) recovers every K-sparse signal of the batch exactly (P17 per image), and each
+    image's result is bit for bit the one it gets alone and in another batch (P8's
+    invariant: images are independent)."""
+    n, M, K, B = 8, 32, 4, 5
+    phi = synth.make_phi(M, n * n, cfg_id=210)
+    xs, ys = [], []
+    for q in range(B):
+        _, s_true = synth.dct_sparse_images(1, n, K, cfg_id=220 + q, return_coeffs=True)
+        x = scipy.fft.idctn(s_true[0], norm="ortho").reshape(-1)
+        xs.append(x)
+        ys.append(orc.measure(phi, x[None])[0])
+    Y = np.stack(ys)
+    X, S, ns = orc.ista_dct_batch(phi, Y, n, n)
+    for q in range(B):
+        assert ns[q] == K
+        assert np.linalg.norm(X[q] - xs[q]) / np.linalg.norm(xs[q]) < 1e-10
+        x1, s1, n1 = orc.ista_dct(phi, Y[q], n, n)
+        assert np.array_equal(x1, X[q]) and np.array_equal(s1, S[q]) and n1 == ns[q]
+    X2, _, _ = orc.ista_dct_batch(phi, Y[[4, 1, 3]], n, n)
+    assert np.array_equal(X2, X[[4, 1, 3]])
+
+
 def test_noise_reaches_the_requested_snr(orc):
     """Sec. 5 / Table 3 noise model: the added noise has exactly the requested SNR and direction."""
     y = synth.normal_values((3, 40), 1.0, 117, 1)
