@@ -130,8 +130,11 @@ dsi_status dsi_measure_noisy(dsi_ctx *ctx, const float *phi, const float *x, con
  * return a prepared network in *out.  The packed copies are owned by the
  * network; `params` may be freed afterwards.  Runs on `stream` and waits for
  * it before returning.  Precisions: DSI_F32 and DSI_F64 for every
- * architecture; DSI_BF16 and DSI_FP8_E4M3 for the paper's architecture
- * (C = {1,64,32,1}, k = 11), else DSI_E_DTYPE. */
+ * architecture; DSI_FP8_E4M3 for the paper's architecture (C = {1,64,32,1},
+ * k = 11); DSI_BF16 for the paper's architecture and for any other stack of
+ * 11 x 11 layers whose hidden widths are 32 or 64 channels (deeper or wider
+ * DeepInverse networks, which Sec. 5 leaves to future work: recovery only, their
+ * training calls return DSI_E_DTYPE); else DSI_E_DTYPE. */
 dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_params *params,
                            dsi_prec prec, dsi_net **out, void *stream);
 /* Re-pack the network's copies from new parameter values (same shapes). Enqueued on stream. */
@@ -159,8 +162,12 @@ dsi_status dsi_net_free(dsi_ctx *ctx, dsi_net *net);
 /* Query the net's precision and description (host outputs, nullable). */
 dsi_status dsi_net_info(const dsi_net *net, dsi_net_desc *desc, dsi_prec *prec);
 
-/* Bytes of training state one batch of B images needs (`saved` of
- * dsi_forward_train).  train = 0 gives the recovery workspace instead. */
+/* Bytes of state one batch of B images needs: train = 1, the saved state of
+ * dsi_forward_train that keeps every activation (recompute = 0); train = 2, the
+ * saved state of the recompute mode (recompute = 1: the proxy x~, the network's
+ * output and, for a trainable FC layer, y -- 2 + 4 bytes per pixel and image in
+ * BF16, against 2 + 128 + 64 + 4 with the hidden activations kept); train = 0, the
+ * recovery workspace of dsi_recover. */
 dsi_status dsi_workspace_size(const dsi_net *net, int B, int train, size_t *bytes);
 /* Grow the context's workspace now to serve batches of up to B images of this
  * net (so later calls do not allocate, e.g. under stream capture). Synchronous. */
@@ -191,18 +198,34 @@ dsi_status dsi_recover_noalloc(dsi_ctx *ctx, const dsi_net *net, const float *y,
 
 /* ------------------------------------------------- Sec. 4: backpropagation */
 /* Forward pass that also keeps, in `saved` (caller-owned device buffer of at
- * least dsi_workspace_size(net, B, 1) bytes), what the backward pass needs. */
+ * least dsi_workspace_size(net, B, 1 + recompute) bytes), what the backward pass
+ * needs.  recompute = 0: every activation.  recompute = 1: only the proxy x~
+ * and the output (and y for a trainable FC layer); the backward pass recomputes
+ * the hidden layers from x~ (Sec. 4's backpropagation needs them; recomputing
+ * trades their memory for one more pass through conv layers 1..L-1).  In this
+ * mode the batch runs in chunks through the context's workspace, as many images
+ * per chunk as dsi_set_recompute_budget allows (the whole batch by default), so
+ * a batch whose activations outgrow the device still trains.  xhat [B][n1][n2]. */
 dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat,
-                             int B, void *saved, size_t saved_bytes, void *stream);
+                             int B, void *saved, size_t saved_bytes, int recompute, void *stream);
 /* Backward pass of a loss with gradient gxhat = dL/dxhat [B][n1][n2] (FP32),
- * from the state dsi_forward_train left in `saved` for the same y and B.
- * Writes dL/dw[l] and dL/db[l] into grads (overwriting) and, if gy is not
- * NULL, dL/dy [B][M].  Parameter gradients are summed over the batch in a
- * fixed order, so repeated calls give identical bits. */
+ * from the state dsi_forward_train left in `saved` for the same y, B and
+ * recompute flag.  Writes dL/dw[l] and dL/db[l] into grads (overwriting) and,
+ * if gy is not NULL, dL/dy [B][M].  Parameter gradients are summed over the
+ * batch in a fixed order, so repeated calls give identical bits.  recompute = 1
+ * recomputes the hidden activations chunk by chunk (chunks as in
+ * dsi_forward_train); with one chunk the gradients are bit-identical to the
+ * recompute = 0 ones, with several the chunks' gradients are added in chunk
+ * order (the same sums, reassociated in FP32). */
 dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, const void *saved,
-                        size_t saved_bytes, int B, const dsi_grads *grads, float *gy,
+                        size_t saved_bytes, int recompute, int B, const dsi_grads *grads, float *gy,
                         void *stream);
-/* Copy activation `layer` of the state dsi_forward_train left in `saved`
+/* Workspace bytes one chunk of the recompute mode may use on this context: the
+ * chunk is the largest number of images whose training state, backward scratch
+ * and gradient buffers fit (at least one image).  0 (the default): the whole
+ * batch is one chunk. */
+dsi_status dsi_set_recompute_budget(dsi_ctx *ctx, size_t bytes);
+/* Copy activation `layer` of the state dsi_forward_train (recompute = 0) left in `saved`
  * (0 = the proxy x~, 1..L-1 = the hidden feature maps after ReLU, L = xhat),
  * converted to FP32, into out [B][C_layer][n1][n2] (planar, device). */
 dsi_status dsi_saved_activation(dsi_ctx *ctx, const dsi_net *net, const void *saved,

@@ -153,6 +153,10 @@ class Context:
         except Exception:
             pass
 
+    def set_recompute_budget(self, nbytes: int):
+        """Workspace bytes one chunk of recompute-mode training may use (0: whole batch)."""
+        _lib.dsi_set_recompute_budget(self.h, int(nbytes))
+
     def measure(self, phi, x, y=None):
         """y = Phi x (Sec. 1). phi [M][N], x [B][N] float32 device tensors."""
         torch = _torch()
@@ -238,14 +242,20 @@ class Net:
         _lib.dsi_recover(self.ctx.h, self.h, _ptr(_f32(y, "y")), _ptr(xhat), B, _stream(self.ctx.device))
         return xhat
 
-    def forward_train(self, y):
+    def saved_bytes(self, B, recompute=False) -> int:
+        """Bytes of the state forward_train keeps for a batch of B images."""
+        return _lib.dsi_workspace_size(self.h, B, 2 if recompute else 1)
+
+    def forward_train(self, y, recompute=False):
+        """xhat and the state the backward pass needs: every activation, or (recompute)
+        only the proxy and the output, the hidden layers being recomputed by backward."""
         torch = _torch()
         B = y.shape[0]
-        nbytes = self.workspace_size(B, True)
+        nbytes = self.saved_bytes(B, recompute)
         saved = torch.empty(nbytes, dtype=torch.uint8, device=y.device)
         xhat = torch.empty((B, self.n1, self.n2), dtype=torch.float32, device=y.device)
         _lib.dsi_forward_train(self.ctx.h, self.h, _ptr(_f32(y, "y")), _ptr(xhat), B, _ptr(saved), nbytes,
-                               _stream(self.ctx.device))
+                               int(recompute), _stream(self.ctx.device))
         return xhat, saved
 
     def saved_activation(self, saved, B, layer):
@@ -257,13 +267,13 @@ class Net:
                                   _stream(self.ctx.device))
         return out
 
-    def backward(self, gxhat, saved, params_like: NetParams, want_gy=False):
+    def backward(self, gxhat, saved, params_like: NetParams, want_gy=False, recompute=False):
         torch = _torch()
         B = gxhat.shape[0]
         g = NetParams.grads_like(params_like, with_fc=bool(self.desc.fc_trainable))
         gy = torch.empty((B, self.M), dtype=torch.float32, device=gxhat.device) if want_gy else None
         _lib.dsi_backward(self.ctx.h, self.h, _ptr(_f32(gxhat.contiguous(), "gxhat")), _ptr(saved),
-                          saved.numel(), B, g.grads_to_c(), _ptr(gy), _stream(self.ctx.device))
+                          saved.numel(), int(recompute), B, g.grads_to_c(), _ptr(gy), _stream(self.ctx.device))
         return g, gy
 
     def loss_grad(self, y, x, params_like: NetParams, want_gy=False):

@@ -28,7 +28,8 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_net_info", "dsi_workspace_size", "dsi_reserve", "dsi_recover",
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
            "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation", "dsi_net_calibrate",
-           "dsi_net_get_scales", "dsi_measure_noisy", "dsi_recover_noalloc"]
+           "dsi_net_get_scales", "dsi_measure_noisy", "dsi_recover_noalloc",
+           "dsi_set_recompute_budget"]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20     # DSI_NOALLOC_SCRATCH_BYTES
 
@@ -89,8 +90,9 @@ def lib() -> ctypes.CDLL:
         "dsi_reserve": (st, [P, P, i, i]),
         "dsi_recover": (st, [P, P, P, P, i, P]),
         "dsi_recover_noalloc": (st, [P, P, P, P, i, P]),
-        "dsi_forward_train": (st, [P, P, P, P, i, P, z, P]),
-        "dsi_backward": (st, [P, P, P, P, z, i, ctypes.POINTER(Params), P, P]),
+        "dsi_forward_train": (st, [P, P, P, P, i, P, z, i, P]),
+        "dsi_backward": (st, [P, P, P, P, z, i, i, ctypes.POINTER(Params), P, P]),
+        "dsi_set_recompute_budget": (st, [P, z]),
         "dsi_loss_grad": (st, [P, P, P, P, i, ctypes.POINTER(Params), P, P, P]),
         "dsi_train_step": (st, [P, P, ctypes.POINTER(Params), ctypes.POINTER(Adam), P, P, i,
                                 ctypes.c_float, P, P]),
@@ -179,12 +181,16 @@ def dsi_recover_noalloc(ctx, net, y, xhat, B, stream):
     call("dsi_recover_noalloc", ctx, net, y, xhat, B, stream)
 
 
-def dsi_forward_train(ctx, net, y, xhat, B, saved, saved_bytes, stream):
-    call("dsi_forward_train", ctx, net, y, xhat, B, saved, saved_bytes, stream)
+def dsi_forward_train(ctx, net, y, xhat, B, saved, saved_bytes, recompute, stream):
+    call("dsi_forward_train", ctx, net, y, xhat, B, saved, saved_bytes, int(recompute), stream)
 
 
-def dsi_backward(ctx, net, gxhat, saved, saved_bytes, B, grads: Params, gy, stream):
-    call("dsi_backward", ctx, net, gxhat, saved, saved_bytes, B, ctypes.byref(grads), gy, stream)
+def dsi_backward(ctx, net, gxhat, saved, saved_bytes, recompute, B, grads: Params, gy, stream):
+    call("dsi_backward", ctx, net, gxhat, saved, saved_bytes, int(recompute), B, ctypes.byref(grads), gy, stream)
+
+
+def dsi_set_recompute_budget(ctx, nbytes):
+    call("dsi_set_recompute_budget", ctx, int(nbytes))
 
 
 def dsi_loss_grad(ctx, net, y, x, B, grads: Params, gy, loss_dev, stream):

@@ -43,11 +43,25 @@ dsi_status fail(dsi_status st, const char *fmt, ...) {
 bool aligned16(const void *p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
 size_t rnd(size_t x) { return (x + 255) & ~size_t(255); }
 
-enum Path { PATH_GENERIC = 0, PATH_PAPER = 1 };
+// PATH_GENERIC: direct kernels, any architecture (FP32, FP64).  PATH_PAPER: the matrix-core
+// kernels of the paper's 1 -> 64 -> 32 -> 1 network (FP32, BF16, FP8; training too).
+// PATH_DEEP: BF16 recovery of other stacks of 11 x 11 layers on the same matrix-core
+// kernels (hidden widths 32 or 64, any depth).
+enum Path { PATH_GENERIC = 0, PATH_PAPER = 1, PATH_DEEP = 2 };
 
 bool is_paper_arch(const dsi_net_desc &d) {
   return d.L == 3 && d.C[0] == 1 && d.C[1] == 64 && d.C[2] == 32 && d.C[3] == 1 && d.k[0] == 11 &&
          d.k[1] == 11 && d.k[2] == 11;
+}
+
+// 1 -> C_1 -> ... -> C_{L-1} -> 1, every filter 11 x 11, every hidden width 32 or 64, L >= 2
+bool is_deep_arch(const dsi_net_desc &d) {
+  if (d.L < 2 || d.C[0] != 1 || d.C[d.L] != 1) return false;
+  for (int l = 0; l < d.L; ++l)
+    if (d.k[l] != 11) return false;
+  for (int l = 1; l < d.L; ++l)
+    if (d.C[l] != 32 && d.C[l] != 64) return false;
+  return true;
 }
 
 size_t elem_size(dsi_prec p) {
@@ -66,6 +80,7 @@ struct dsi_ctx {
   void *ws = nullptr;
   size_t ws_bytes = 0;
   void *fixed_ws = nullptr;  // device address of the fixed workspace array (dsi_recover_noalloc)
+  size_t rc_budget = 0;      // workspace bytes a recompute-mode chunk may use (0: whole batch)
   // stage timing (benchmarking): one set of events per timed forward pass
   int timing = 0;
   std::vector<std::vector<hipEvent_t>> ev;
@@ -108,6 +123,10 @@ struct dsi_net {
   // paper path
   void *wp1 = nullptr, *wp2 = nullptr, *wp3 = nullptr;  // packed (compute precision)
   float *bp[3] = {};  // fp32 biases: dsi_params layout; layer 2 per-pixel in fragment order [H][W][32]
+  // PATH_DEEP: packed BF16 weights and fp32 biases of every layer (hidden layers' per-pixel
+  // biases in the conv_mid epilogue's fragment order)
+  void *wl[DSI_MAX_LAYERS] = {};
+  float *bl[DSI_MAX_LAYERS] = {};
   void *wp3f = nullptr, *wp2f = nullptr, *wp1f = nullptr;  // packed data-gradient operators
   float w_scale_fc = 1.0f, w_scale_2 = 1.0f;              // FP8 per-tensor weight scales
   unsigned *amax_dev = nullptr;                            // FP8: device scratch for amax
@@ -189,6 +208,22 @@ Layout layout(const dsi_net &n, int B, int train) {
   return L;
 }
 
+// Saved state of the recompute mode for B images: the proxy x~ [B][N] (compute
+// precision), the output [B][N] of the last layer (FP32; FP64 for DSI_F64) and, for a
+// trainable FC layer, y [B][M] -- the parts of layout(n, B, 1) that are per image and
+// not recomputed.  The hidden activations are recomputed from x~ by the backward pass.
+Layout layout_rc(const dsi_net &n, int B) {
+  Layout L;
+  const size_t N = (size_t)n.N;
+  const size_t es_last = n.prec == DSI_F64 ? 8 : 4;
+  size_t off = 0;
+  L.xt = off; off += rnd((size_t)B * N * n.es);
+  L.act[n.d.L] = off; off += rnd((size_t)B * N * es_last);
+  if (n.d.fc_trainable) { L.ykeep = off; off += rnd((size_t)B * n.d.M * 4); }
+  L.end = off;
+  return L;
+}
+
 template <typename T> T *at(void *base, size_t off) { return reinterpret_cast<T *>((char *)base + off); }
 
 dsi_status ensure_ws(dsi_ctx *ctx, size_t bytes) {
@@ -222,6 +257,10 @@ void free_net_buffers(dsi_net *n) {
   { void *a = n->amax_dev; f(a); n->amax_dev = nullptr; }
   for (int l = 0; l < 3; ++l) {
     void *a = n->bp[l]; f(a); n->bp[l] = nullptr;
+  }
+  for (int l = 0; l < DSI_MAX_LAYERS; ++l) {
+    f(n->wl[l]);
+    void *a = n->bl[l]; f(a); n->bl[l] = nullptr;
   }
 }
 
@@ -305,6 +344,16 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with
     }
     return DSI_OK;
   }
+  if (n->path == PATH_DEEP) {
+    for (int l = 0; l < d.L; ++l) {
+      if (l == 0) HIPCHK(dsi::pack_first(p->w[0], n->wl[0], d.C[1], 0, 1, s));
+      else if (l == d.L - 1) HIPCHK(dsi::pack_last(p->w[l], n->wl[l], d.C[l], 0, 1, s));
+      else HIPCHK(dsi::pack_mid(p->w[l], n->wl[l], d.C[l], d.C[l + 1], 0, 1, s));
+      if (l > 0 && l < d.L - 1 && d.bias_per_pixel) HIPCHK(dsi::pack_bias_frag(p->b[l], n->bl[l], d.C[l + 1], (long)HW, s));
+      else HIPCHK(hipMemcpyAsync(n->bl[l], p->b[l], bcount(d, l) * 4, hipMemcpyDeviceToDevice, s));
+    }
+    return DSI_OK;
+  }
   // forward operators, data-gradient operators (layer 3: 32 <- 1, layer 2: 64 <- 32,
   // layer 1: 1 <- 64) and the biases (layer 2's per-pixel bias in the conv2 epilogue's
   // fragment order, the others planar [C][H][W]), in one launch
@@ -322,22 +371,63 @@ dsi_status pack_params(dsi_net *n, const dsi_params *p, hipStream_t s, bool with
   return DSI_OK;
 }
 
+// ------------------------------------------------------- recomputation
+// The hidden layers 1..L-1 from the proxy x~ at L.xt (FP32 and BF16 nets; FP64 is
+// handled in forward_impl): the same launches as the forward pass, so the recomputed
+// activations are bit-identical to the ones a forward pass keeps.
+dsi_status hidden_impl(const dsi_net *n, int B, void *base, const Layout &L, hipStream_t s) {
+  const dsi_net_desc &d = n->d;
+  const int H = d.n1, W = d.n2;
+  if (n->path == PATH_GENERIC) {
+    const float *a = at<float>(base, L.xt);
+    for (int l = 0; l + 1 < d.L; ++l) {
+      float *o = at<float>(base, L.act[l + 1]);
+      HIPCHK((dsi::conv_fwd_direct<float, float, float, float>(
+          a, ActView{d.C[l], H, W, 0}, (const float *)n->w[l], (const float *)n->b[l], d.bias_per_pixel, 1,
+          o, ActView{d.C[l + 1], H, W, 0}, B, d.k[l], s)));
+      a = o;
+    }
+    return DSI_OK;
+  }
+  if (n->prec == DSI_BF16) {
+    bf16 *xt = at<bf16>(base, L.xt), *a1 = at<bf16>(base, L.act[1]), *a2 = at<bf16>(base, L.act[2]);
+    HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, bf16>(xt, (const bf16 *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
+                                                               nullptr, a1, B, H, W, s)));
+    HIPCHK((dsi::conv_mid<bf16, 64, 32, dsi::EPI_BIAS, bf16>(a1, (const bf16 *)n->wp2, n->bp[1],
+                                                            d.bias_per_pixel, 1, nullptr, a2, B, H, W, s)));
+    return DSI_OK;
+  }
+  if (n->prec == DSI_F32) {
+    float *xt = at<float>(base, L.xt), *a1 = at<float>(base, L.act[1]), *a2 = at<float>(base, L.act[2]);
+    HIPCHK((dsi::conv_first<float, 64, dsi::EPI_BIAS, float, float>(xt, (const float *)n->wp1, n->bp[0], d.bias_per_pixel, 1,
+                                                               nullptr, a1, B, H, W, s)));
+    HIPCHK((dsi::conv_mid<float, 64, 32, dsi::EPI_BIAS, float>(a1, (const float *)n->wp2, n->bp[1],
+                                                              d.bias_per_pixel, 1, nullptr, a2, B, H, W, s)));
+    return DSI_OK;
+  }
+  return fail(DSI_E_DTYPE, "recomputation runs in FP32, BF16 or FP64");
+}
+
 // ---------------------------------------------------------------- forward
 // Runs the proxy and every conv layer; keeps activations in ws at L (train or not).
+// hidden_only: the proxy x~ is already at L.xt and only the hidden layers 1..L-1 run
+// (the recomputation of the backward pass); y, xhat are then unused.
 dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *xhat, int B, void *base,
-                        const Layout &L, hipStream_t s) {
+                        const Layout &L, hipStream_t s, bool hidden_only = false) {
   const dsi_net_desc &d = n->d;
   const int N = n->N, H = d.n1, W = d.n2, M = d.M;
-  (void)ctx;
-  if (L.ykeep != SIZE_MAX)
+  const int nconv = hidden_only ? d.L - 1 : d.L;
+  if (L.ykeep != SIZE_MAX && !hidden_only)
     HIPCHK(hipMemcpyAsync(at<float>(base, L.ykeep), y, (size_t)B * M * 4, hipMemcpyDeviceToDevice, s));
   if (n->prec == DSI_F64) {
     double *y64 = at<double>(base, L.ypad);
     double *xt = at<double>(base, L.xt);
-    HIPCHK(dsi::cast_f32_f64(y, y64, (long)B * M, s));
-    HIPCHK(dsi::gemm_nt_f64(y64, M, (const double *)n->wfc, M, xt, N, B, N, M, s));
+    if (!hidden_only) {
+      HIPCHK(dsi::cast_f32_f64(y, y64, (long)B * M, s));
+      HIPCHK(dsi::gemm_nt_f64(y64, M, (const double *)n->wfc, M, xt, N, B, N, M, s));
+    }
     const double *a = xt;
-    for (int l = 0; l < d.L; ++l) {
+    for (int l = 0; l < nconv; ++l) {
       double *o = at<double>(base, L.act[l + 1]);
       const int relu = (l < d.L - 1) || d.relu_last;
       HIPCHK((dsi::conv_fwd_direct<double, double, double, double>(
@@ -345,9 +435,10 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
           relu, o, ActView{d.C[l + 1], H, W, 0}, B, d.k[l], s)));
       a = o;
     }
-    if (xhat) HIPCHK(dsi::cast_f64_f32(a, xhat, (long)B * N, s));
+    if (xhat && !hidden_only) HIPCHK(dsi::cast_f64_f32(a, xhat, (long)B * N, s));
     return DSI_OK;
   }
+  if (hidden_only) return hidden_impl(n, B, base, L, s);
   // proxy x~ = W_fc y (K padded to Mpad with zeros)
   const bool direct_y = ((M % 16 == 0) && aligned16(y)) || n->prec == DSI_FP8_E4M3 || n->prec == DSI_BF16;
   const float *yk = y;
@@ -373,6 +464,38 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
           o, ActView{d.C[l + 1], H, W, 0}, B, d.k[l], s)));
       a = o;
     }
+  } else if (n->path == PATH_DEEP) {
+    bf16 *yp = at<bf16>(base, L.ypad), *xt = at<bf16>(base, L.xt);
+    HIPCHK(dsi::pack_frag_bf16(y, M, B, M, rnd32(B), n->Mpad, yp, s));
+    HIPCHK(dsi::gemm_frag_bf16(yp, (const bf16 *)n->wfc, xt, N, B, N, n->Mpad / 16, s));
+    clk.mark();
+    const bf16 *a = xt;
+    for (int l = 0; l < d.L; ++l) {
+      const bf16 *wl = (const bf16 *)n->wl[l];
+      const float *bl = n->bl[l];
+      const int ci = d.C[l], co = d.C[l + 1], bpp = d.bias_per_pixel;
+      if (l == d.L - 1) {
+        if (ci == 32) HIPCHK((dsi::conv_last<bf16, 32>(a, wl, bl, bpp, d.relu_last, xout_last, B, H, W, s)));
+        else HIPCHK((dsi::conv_last<bf16, 64>(a, wl, bl, bpp, d.relu_last, xout_last, B, H, W, s)));
+        break;
+      }
+      bf16 *o = at<bf16>(base, L.act[l + 1]);
+      if (l == 0) {
+        if (co == 32) HIPCHK((dsi::conv_first<bf16, 32, dsi::EPI_BIAS, bf16, bf16>(a, wl, bl, bpp, 1, nullptr, o, B, H, W, s)));
+        else HIPCHK((dsi::conv_first<bf16, 64, dsi::EPI_BIAS, bf16, bf16>(a, wl, bl, bpp, 1, nullptr, o, B, H, W, s)));
+      } else if (ci == 32 && co == 32) {
+        HIPCHK((dsi::conv_mid<bf16, 32, 32, dsi::EPI_BIAS, bf16>(a, wl, bl, bpp, 1, nullptr, o, B, H, W, s)));
+      } else if (ci == 32) {
+        HIPCHK((dsi::conv_mid<bf16, 32, 64, dsi::EPI_BIAS, bf16>(a, wl, bl, bpp, 1, nullptr, o, B, H, W, s)));
+      } else if (co == 32) {
+        HIPCHK((dsi::conv_mid<bf16, 64, 32, dsi::EPI_BIAS, bf16>(a, wl, bl, bpp, 1, nullptr, o, B, H, W, s)));
+      } else {
+        HIPCHK((dsi::conv_mid<bf16, 64, 64, dsi::EPI_BIAS, bf16>(a, wl, bl, bpp, 1, nullptr, o, B, H, W, s)));
+      }
+      clk.mark();
+      a = o;
+    }
+    clk.mark();
   } else if (n->prec == DSI_FP8_E4M3) {
     // y -> e4m3 codes (scale s_y), FP8 proxy GEMM -> x~ BF16, conv1 BF16 -> a1 e4m3 codes (scale s_a1),
     // conv2 FP8 -> a2 BF16, conv3 BF16
@@ -681,14 +804,17 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
   const bool paper = is_paper_arch(*desc);
   if (prec != DSI_F32 && prec != DSI_F64 && prec != DSI_BF16 && prec != DSI_FP8_E4M3)
     return fail(DSI_E_DTYPE, "unknown precision %d", (int)prec);
-  if ((prec == DSI_BF16 || prec == DSI_FP8_E4M3) && !paper)
-    return fail(DSI_E_DTYPE, "BF16/FP8 need the paper's architecture (C = 1,64,32,1; k = 11)");
+  const bool deep = !paper && prec == DSI_BF16 && is_deep_arch(*desc);
+  if (prec == DSI_FP8_E4M3 && !paper)
+    return fail(DSI_E_DTYPE, "FP8 needs the paper's architecture (C = 1,64,32,1; k = 11)");
+  if (prec == DSI_BF16 && !paper && !deep)
+    return fail(DSI_E_DTYPE, "BF16 needs 11 x 11 filters and hidden widths of 32 or 64 channels");
   if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
   dsi_net *n = new (std::nothrow) dsi_net;
   if (!n) return fail(DSI_E_NOMEM, "host allocation failed");
   n->d = *desc;
   n->prec = prec;
-  n->path = (paper && prec != DSI_F64) ? PATH_PAPER : PATH_GENERIC;
+  n->path = (paper && prec != DSI_F64) ? PATH_PAPER : deep ? PATH_DEEP : PATH_GENERIC;
   n->N = desc->n1 * desc->n2;
   n->Mpad = prec == DSI_F64 ? desc->M : prec == DSI_FP8_E4M3 ? (desc->M + 63) / 64 * 64 : (desc->M + 15) / 16 * 16;
   n->es = elem_size(prec);
@@ -701,6 +827,12 @@ dsi_status dsi_net_prepare(dsi_ctx *ctx, const dsi_net_desc *desc, const dsi_par
     for (int l = 0; l < d.L; ++l) {
       A(&n->w[l], wcount(d, l) * n->es);
       A(&n->b[l], bcount(d, l) * n->es);
+    }
+  } else if (n->path == PATH_DEEP) {
+    for (int l = 0; l < d.L; ++l) {
+      const size_t nw = l == 0 ? (size_t)11 * (d.C[1] / 32) * 64 * 8 : (size_t)wcount(d, l);
+      A(&n->wl[l], nw * 2);
+      A((void **)&n->bl[l], bcount(d, l) * 4);
     }
   } else if (prec == DSI_FP8_E4M3) {
     A(&n->wp1, (size_t)11 * 2 * 64 * 8 * 2);
@@ -811,7 +943,8 @@ dsi_status dsi_net_info(const dsi_net *net, dsi_net_desc *desc, dsi_prec *prec) 
 dsi_status dsi_workspace_size(const dsi_net *net, int B, int train, size_t *bytes) {
   if (!net || !bytes) return fail(DSI_E_NULL, "net and bytes must be non-NULL");
   if (B < 0) return fail(DSI_E_SHAPE, "B = %d", B);
-  *bytes = layout(*net, B, train ? 1 : 0).end;
+  if (train < 0 || train > 2) return fail(DSI_E_SHAPE, "train = %d must be 0, 1 or 2", train);
+  *bytes = train == 2 ? layout_rc(*net, B).end : layout(*net, B, train).end;
   return DSI_OK;
 }
 
@@ -854,16 +987,83 @@ dsi_status dsi_recover_noalloc(dsi_ctx *ctx, const dsi_net *net, const float *y,
   return forward_impl(nullptr, net, y, xhat, B, ctx->fixed_ws, L, (hipStream_t)stream);
 }
 
+namespace {
+// bytes of gradient buffers for every parameter tensor (and W_fc when it trains)
+size_t grad_bytes(const dsi_net &n) {
+  size_t g = 0;
+  for (int l = 0; l < n.d.L; ++l) g += rnd(wcount(n.d, l) * 4) + rnd(bcount(n.d, l) * 4);
+  if (n.d.fc_trainable) g += rnd((size_t)n.N * n.d.M * 4);
+  return g;
+}
+
+// workspace of one recompute-mode chunk of Bc images (of a batch of B): the full
+// training state of the chunk, the backward scratch and, when the batch takes more
+// than one chunk, the gradient buffers of a later chunk
+size_t rc_chunk_bytes(const dsi_net &n, int Bc, int B) {
+  return layout(n, Bc, 1).end + backward_scratch_bytes(n, Bc) + (Bc < B ? grad_bytes(n) : 0);
+}
+
+// images per chunk: the whole batch, or the largest chunk whose workspace fits the
+// context's recompute budget (at least one image)
+int rc_chunk(const dsi_ctx *ctx, const dsi_net &n, int B) {
+  if (ctx->rc_budget == 0 || rc_chunk_bytes(n, B, B) <= ctx->rc_budget) return B;
+  int lo = 1, hi = B - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) / 2;
+    if (rc_chunk_bytes(n, mid, B) <= ctx->rc_budget) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+size_t off_xt(const dsi_net &n, int b0) { return (size_t)b0 * n.N * n.es; }
+size_t off_last(const dsi_net &n, int b0) { return (size_t)b0 * n.N * (n.prec == DSI_F64 ? 8 : 4); }
+
+// recompute-mode forward: chunks of the batch through the context's workspace, each
+// chunk's proxy, output (and y) copied into the caller's saved state
+dsi_status forward_train_rc(dsi_ctx *ctx, const dsi_net *n, const float *y, float *xhat, int B, void *saved,
+                            hipStream_t s) {
+  const Layout R = layout_rc(*n, B);
+  const int chunk = rc_chunk(ctx, *n, B), N = n->N, M = n->d.M, L = n->d.L;
+  const Layout W = layout(*n, chunk, 1);
+  dsi_status st = ensure_ws(ctx, rc_chunk_bytes(*n, chunk, B));
+  if (st != DSI_OK) return st;
+  for (int b0 = 0; b0 < B; b0 += chunk) {
+    const int bc = std::min(chunk, B - b0);
+    const Layout Lc = layout(*n, bc, 1);
+    if ((st = forward_impl(ctx, n, y + (size_t)b0 * M, xhat + (size_t)b0 * N, bc, ctx->ws, Lc, s)) != DSI_OK) return st;
+    HIPCHK(hipMemcpyAsync(at<char>(saved, R.xt + off_xt(*n, b0)), at<char>(ctx->ws, Lc.xt), off_xt(*n, bc),
+                          hipMemcpyDeviceToDevice, s));
+    HIPCHK(hipMemcpyAsync(at<char>(saved, R.act[L] + off_last(*n, b0)), at<char>(ctx->ws, Lc.act[L]),
+                          off_last(*n, bc), hipMemcpyDeviceToDevice, s));
+    if (R.ykeep != SIZE_MAX)
+      HIPCHK(hipMemcpyAsync(at<float>(saved, R.ykeep) + (size_t)b0 * M, y + (size_t)b0 * M, (size_t)bc * M * 4,
+                            hipMemcpyDeviceToDevice, s));
+  }
+  (void)W;
+  return DSI_OK;
+}
+}  // namespace
+
+dsi_status dsi_set_recompute_budget(dsi_ctx *ctx, size_t bytes) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  ctx->rc_budget = bytes;
+  return DSI_OK;
+}
+
 dsi_status dsi_forward_train(dsi_ctx *ctx, const dsi_net *net, const float *y, float *xhat, int B,
-                             void *saved, size_t saved_bytes, void *stream) {
+                             void *saved, size_t saved_bytes, int recompute, void *stream) {
   if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
   if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
+  if (net->path == PATH_DEEP)
+    return fail(DSI_E_DTYPE, "BF16 training needs the paper's architecture; other stacks train in FP32 or FP64");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1 for training", B);
+  if (recompute != 0 && recompute != 1) return fail(DSI_E_SHAPE, "recompute = %d must be 0 or 1", recompute);
   if (!y || !xhat || !saved) return fail(DSI_E_NULL, "y, xhat and saved must be non-NULL");
   if (!aligned16(y) || !aligned16(xhat) || !aligned16(saved)) return fail(DSI_E_ALIGN, "buffers must be 16-byte aligned");
-  const Layout L = layout(*net, B, 1);
+  const Layout L = recompute ? layout_rc(*net, B) : layout(*net, B, 1);
   if (saved_bytes < L.end) return fail(DSI_E_SHAPE, "saved buffer has %zu bytes, needs %zu", saved_bytes, L.end);
   if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  if (recompute) return forward_train_rc(ctx, net, y, xhat, B, saved, (hipStream_t)stream);
   return forward_impl(ctx, net, y, xhat, B, saved, L, (hipStream_t)stream);
 }
 
@@ -890,32 +1090,97 @@ dsi_status ensure_wfcT(dsi_net *n, hipStream_t s) {
 }
 }  // namespace
 
+namespace {
+// byte offset of gz (dL/dz of the last layer) in a backward scratch area of `scratch` bytes
+size_t gz_offset(const dsi_net &n, int B, size_t scratch) {
+  return scratch - rnd((size_t)B * n.N * (n.prec == DSI_F64 ? 8 : 4)) - rnd((size_t)B * 4 * 8) - 256;
+}
+
+dsi_status mask_last(const dsi_net &n, const float *gxhat, const void *last, void *gz, long count, hipStream_t s) {
+  if (n.prec == DSI_F64)
+    HIPCHK(dsi::relu_mask_f64(gxhat, n.d.relu_last ? (const double *)last : nullptr, (double *)gz, count, s));
+  else
+    HIPCHK(dsi::relu_mask_f32(gxhat, n.d.relu_last ? (const float *)last : nullptr, (float *)gz, count, s));
+  return DSI_OK;
+}
+
+// recompute-mode backward: per chunk, the proxy (and y) come back from the saved
+// state, the hidden layers are recomputed, and the chunk's backward pass runs; the
+// first chunk writes the parameter gradients, later chunks add theirs
+dsi_status backward_rc(dsi_ctx *ctx, const dsi_net *n, const float *gxhat, const void *saved, int B,
+                       const dsi_grads *grads, float *gy, hipStream_t s) {
+  const Layout R = layout_rc(*n, B);
+  const dsi_net_desc &d = n->d;
+  const int chunk = rc_chunk(ctx, *n, B), N = n->N, M = d.M, L = d.L;
+  dsi_status st = ensure_ws(ctx, rc_chunk_bytes(*n, chunk, B));
+  if (st != DSI_OK) return st;
+  void *sv = const_cast<void *>(saved);
+  // gradient buffers of the later chunks, after the largest chunk's state and scratch
+  dsi_grads tmp{};
+  const bool want_fc = d.fc_trainable && grads->w_fc;
+  {
+    size_t off = layout(*n, chunk, 1).end + backward_scratch_bytes(*n, chunk);
+    for (int l = 0; l < L; ++l) {
+      tmp.w[l] = at<float>(ctx->ws, off); off += rnd(wcount(d, l) * 4);
+      tmp.b[l] = at<float>(ctx->ws, off); off += rnd(bcount(d, l) * 4);
+    }
+    if (want_fc) tmp.w_fc = at<float>(ctx->ws, off);
+  }
+  for (int b0 = 0; b0 < B; b0 += chunk) {
+    const int bc = std::min(chunk, B - b0);
+    const Layout Lc = layout(*n, bc, 1);
+    const size_t scratch = backward_scratch_bytes(*n, bc);
+    void *scr = at<char>(ctx->ws, Lc.end);
+    HIPCHK(hipMemcpyAsync(at<char>(ctx->ws, Lc.xt), at<char>(sv, R.xt + off_xt(*n, b0)), off_xt(*n, bc),
+                          hipMemcpyDeviceToDevice, s));
+    if (Lc.ykeep != SIZE_MAX)
+      HIPCHK(hipMemcpyAsync(at<float>(ctx->ws, Lc.ykeep), at<float>(sv, R.ykeep) + (size_t)b0 * M,
+                            (size_t)bc * M * 4, hipMemcpyDeviceToDevice, s));
+    if ((st = forward_impl(nullptr, n, nullptr, nullptr, bc, ctx->ws, Lc, s, true)) != DSI_OK) return st;
+    void *gz = at<char>(scr, gz_offset(*n, bc, scratch));
+    if ((st = mask_last(*n, gxhat + (size_t)b0 * N, at<char>(sv, R.act[L] + off_last(*n, b0)), gz, (long)bc * N, s)) !=
+        DSI_OK)
+      return st;
+    dsi_grads gc = b0 == 0 ? *grads : tmp;
+    if (!want_fc) gc.w_fc = nullptr;
+    if ((st = backward_impl(ctx, n, gz, ctx->ws, Lc, bc, &gc, gy ? gy + (size_t)b0 * M : nullptr, scr, s)) != DSI_OK)
+      return st;
+    if (b0 > 0) {
+      for (int l = 0; l < L; ++l) {
+        HIPCHK(dsi::add_f32(grads->w[l], tmp.w[l], wcount(d, l), s));
+        HIPCHK(dsi::add_f32(grads->b[l], tmp.b[l], bcount(d, l), s));
+      }
+      if (want_fc) HIPCHK(dsi::add_f32(grads->w_fc, tmp.w_fc, (long)N * M, s));
+    }
+  }
+  return DSI_OK;
+}
+}  // namespace
+
 dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, const void *saved,
-                        size_t saved_bytes, int B, const dsi_grads *grads, float *gy, void *stream) {
+                        size_t saved_bytes, int recompute, int B, const dsi_grads *grads, float *gy,
+                        void *stream) {
   if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
   if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
+  if (net->path == PATH_DEEP)
+    return fail(DSI_E_DTYPE, "BF16 training needs the paper's architecture; other stacks train in FP32 or FP64");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
+  if (recompute != 0 && recompute != 1) return fail(DSI_E_SHAPE, "recompute = %d must be 0 or 1", recompute);
   if (!gxhat || !saved) return fail(DSI_E_NULL, "gxhat and saved must be non-NULL");
   dsi_status st = check_grads(net, grads);
   if (st != DSI_OK) return st;
-  const Layout L = layout(*net, B, 1);
+  const Layout L = recompute ? layout_rc(*net, B) : layout(*net, B, 1);
   if (saved_bytes < L.end) return fail(DSI_E_SHAPE, "saved buffer has %zu bytes, needs %zu", saved_bytes, L.end);
   if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
   hipStream_t s = (hipStream_t)stream;
   if (gy && (st = ensure_wfcT(const_cast<dsi_net *>(net), s)) != DSI_OK) return st;
+  if (recompute) return backward_rc(ctx, net, gxhat, saved, B, grads, gy, s);
   const size_t scratch = backward_scratch_bytes(*net, B);
   if ((st = ensure_ws(ctx, scratch)) != DSI_OK) return st;
-  const dsi_net_desc &d = net->d;
-  const int N = net->N;
   // gz of the last layer: gxhat masked by the last ReLU, in the path's gradient precision
-  const size_t gz_off = scratch - rnd((size_t)B * N * (net->prec == DSI_F64 ? 8 : 4)) - rnd((size_t)B * 4 * 8) - 256;
-  void *gz = at<char>(ctx->ws, gz_off);
-  const void *last = at<char>(const_cast<void *>(saved), L.act[d.L]);
-  const long n = (long)B * N;
-  if (net->prec == DSI_F64)
-    HIPCHK(dsi::relu_mask_f64(gxhat, d.relu_last ? (const double *)last : nullptr, (double *)gz, n, s));
-  else
-    HIPCHK(dsi::relu_mask_f32(gxhat, d.relu_last ? (const float *)last : nullptr, (float *)gz, n, s));
+  void *gz = at<char>(ctx->ws, gz_offset(*net, B, scratch));
+  const void *last = at<char>(const_cast<void *>(saved), L.act[net->d.L]);
+  if ((st = mask_last(*net, gxhat, last, gz, (long)B * net->N, s)) != DSI_OK) return st;
   return backward_impl(ctx, net, gz, saved, L, B, grads, gy, ctx->ws, s);
 }
 
@@ -1013,6 +1278,8 @@ dsi_status dsi_loss_grad(dsi_ctx *ctx, dsi_net *net, const float *y, const float
                          float *gy, double *loss_dev, void *stream) {
   if (!ctx || !net) return fail(DSI_E_NULL, "ctx and net must be non-NULL");
   if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
+  if (net->path == PATH_DEEP)
+    return fail(DSI_E_DTYPE, "BF16 training needs the paper's architecture; other stacks train in FP32 or FP64");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
   if (!y || !x) return fail(DSI_E_NULL, "y and x must be non-NULL");
   if (!aligned16(y) || !aligned16(x)) return fail(DSI_E_ALIGN, "y and x must be 16-byte aligned");
@@ -1026,6 +1293,8 @@ dsi_status dsi_train_step(dsi_ctx *ctx, dsi_net *net, const dsi_params *params, 
                           const float *x, int B, float lr, double *loss_dev, void *stream) {
   if (!ctx || !net || !opt) return fail(DSI_E_NULL, "ctx, net and opt must be non-NULL");
   if (net->prec == DSI_FP8_E4M3) return fail(DSI_E_DTYPE, "training runs in FP32, BF16 or FP64; FP8 nets recover only");
+  if (net->path == PATH_DEEP)
+    return fail(DSI_E_DTYPE, "BF16 training needs the paper's architecture; other stacks train in FP32 or FP64");
   if (B < 1) return fail(DSI_E_SHAPE, "B = %d must be >= 1", B);
   if (!y || !x) return fail(DSI_E_NULL, "y and x must be non-NULL");
   dsi_status st = check_params(net->d, params);

@@ -1065,6 +1065,11 @@ template hipError_t conv_last<float, 64>(const float *, const float *, const flo
 template hipError_t conv_first<bf16, 64, EPI_BIAS, bf16, u8>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, u8 *, int, int, int, hipStream_t, float);
 template hipError_t conv_mid<u8, 64, 32, EPI_BIAS, bf16>(const u8 *, const u8 *, const float *, int, int, const u8 *, bf16 *, int, int, int, hipStream_t, float);
 template hipError_t conv_last<bf16, 32>(const bf16 *, const bf16 *, const float *, int, int, float *, int, int, int, hipStream_t);
+// deeper or wider stacks of 11 x 11 layers with 32 or 64 hidden channels (BF16 recovery)
+template hipError_t conv_first<bf16, 32, EPI_BIAS, bf16, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<bf16, 32, 32, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<bf16, 32, 64, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
+template hipError_t conv_mid<bf16, 64, 64, EPI_BIAS, bf16>(const bf16 *, const bf16 *, const float *, int, int, const bf16 *, bf16 *, int, int, int, hipStream_t, float);
 template hipError_t conv_last<float, 32>(const float *, const float *, const float *, int, int, float *, int, int, int, hipStream_t);
 
 }  // namespace dsi

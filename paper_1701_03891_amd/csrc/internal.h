@@ -89,6 +89,7 @@ hipError_t fc_wgrad_f64(const double *g, const float *y, long ldy, int B, int N,
 hipError_t add_noise(float *y, const float *e, int B, int M, double snr_db, hipStream_t s);
 hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hipStream_t s);
 hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, hipStream_t s);
+hipError_t add_f32(float *dst, const float *src, long n, hipStream_t s);
 hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float lr, float b1, float b2,
                     float eps, float c1, float c2, hipStream_t s);
 struct AdamSeg {

@@ -480,6 +480,16 @@ hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, h
   return hipGetLastError();
 }
 
+// dst += src (the gradients of a later chunk of a batch added to the earlier chunks')
+__global__ void add_f32_kernel(float *__restrict__ dst, const float *__restrict__ src, long n) {
+  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
+  if (idx < n) dst[idx] += src[idx];
+}
+hipError_t add_f32(float *dst, const float *src, long n, hipStream_t s) {
+  if (n > 0) add_f32_kernel<<<GRID1(n), 0, s>>>(dst, src, n);
+  return hipGetLastError();
+}
+
 // saved activation -> planar fp32 [B][C][H][W]
 template <typename TI>
 __global__ void unpack_act_kernel(const TI *__restrict__ in, ActView vi, float *__restrict__ out, int B) {

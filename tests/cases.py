@@ -129,13 +129,13 @@ def fp8_scales_from_oracle(case, margin=1.05):
     return [pow2_scale(margin * np.abs(case.y).max()), 1.0, pow2_scale(margin * a1max), 1.0]
 
 
-def quant_for(prec, scales=None):
-    """The oracle's model of a precision variant.  scales: the FP8 net's
-    {W_fc, W2, s_y, s_x~, s_a1, s_a2} (Net.scales())."""
+def quant_for(prec, scales=None, L=3):
+    """The oracle's model of a precision variant of an L-layer network.  scales: the FP8
+    net's {W_fc, W2, s_y, s_x~, s_a1, s_a2} (Net.scales())."""
     if prec == "f32":
-        return oracle.Quant.fp32()
+        return oracle.Quant.fp32(L)
     if prec == "bf16":
-        return oracle.Quant.bf16()
+        return oracle.Quant.bf16(L)
     if prec == "fp8":
         s_fc, s_w2, s_y, _, s_a1 = (float(v) for v in scales[:5])
         return oracle.Quant.fp8(s_y, s_fc, s_a1, s_w2)
@@ -155,7 +155,7 @@ def check_recovery(case, got, prec, idx=None, scales=None, label=""):
     else:
         y = case.y if idx is None else case.y[idx]
         _, sig = oracle.forward_q(case.oracle_net(), case.phi.T, case.w, case.oracle_bias(), y,
-                                  quant_for(prec, scales), want_sigma=True)
+                                  quant_for(prec, scales, len(case.k)), want_sigma=True)
         allowed = SIGMA_GATE * sig + 2.0 ** -22 * np.abs(ref) + 1e-12 * rms
     ratio = np.abs(got - ref) / allowed
     worst = np.unravel_index(np.argmax(ratio), ratio.shape)

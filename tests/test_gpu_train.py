@@ -5,13 +5,19 @@ Gradient tolerances (norm-wise relative error per tensor): FP32 <= 1e-5 and
 the FP64 checking path <= 1e-6 (its gradients come back as float32) against
 the oracle's FP64 gradients for the same fp32 inputs.
 
-BF16: the gradient is a discontinuous function of the forward activations
-(ReLU kinks), and a BF16 forward pass moves the active set of the few units
-whose pre-activation lies within rounding of zero.  So the BF16 backward
-kernels are held to 2e-2 per tensor against the oracle's FP64
+The gradient is a discontinuous function of the forward activations (ReLU
+kinks): a forward pass in reduced precision moves the active set of the few
+units whose pre-activation lies within rounding of zero, and each such flip
+changes a whole term of the gradient sums.  So the backward kernels are held
+to the per-tensor tolerance (BF16 2e-2, FP32 1e-5) against the oracle's FP64
 backpropagation evaluated on the SAME forward state (the GPU's own saved
-activations, unpacked through dsi_saved_activation), and the end-to-end
-BF16-vs-FP64 gradient error is reported with a looser bound.
+activations, unpacked through dsi_saved_activation).  The end-to-end error
+against the FP64 oracle's own forward state is then bounded by the tolerance
+plus 3 sqrt(f), f the measured fraction of hidden units whose activity differs
+between the two forward states: a flipped unit removes or adds one term of the
+random-sign sums that make up a gradient entry, so the norm-wise relative
+change of a gradient tensor is about sqrt(f) (e.g. f ~ 3e-3 in BF16 gives
+~5.5e-2, the size observed on the per-pixel bias gradients).
 """
 import numpy as np
 import pytest
@@ -82,45 +88,64 @@ def _check(gpu, ref, tol, label):
     assert not bad, (label, bad)
 
 
-# end-to-end BF16 vs FP64 bounds (mask flips included); weights / per-pixel tensors
-E2E_BF16 = {"loss": 2e-2, "w": 6e-2, "b": 1.2e-1, "y": 1e-1}
-
-
-def _gpu_grads_same_state(ctx, case, want_gy=False):
-    """BF16 GPU gradients and the oracle's FP64 backpropagation on the GPU's forward state."""
+def _gpu_grads_same_state(ctx, case, want_gy=False, prec="bf16"):
+    """GPU gradients, the oracle's FP64 backpropagation on the GPU's forward state, and
+    that forward state (activations a_0..a_L as float64, [layer][image])."""
     import torch
 
     import oracle
     params = case.torch_params()
-    net = ctx.prepare(case.n1, case.n2, case.M, params, prec="bf16", C=case.C, k=case.k,
+    net = ctx.prepare(case.n1, case.n2, case.M, params, prec=prec, C=case.C, k=case.k,
                       bias_per_pixel=case.bias_per_pixel, relu_last=case.relu_last)
     y, B = _t(case.y), case.B
+    L = len(case.k)
     xh, saved = net.forward_train(y)
-    acts = [net.saved_activation(saved, B, l).cpu().numpy().astype(np.float64) for l in range(4)]
+    acts = [net.saved_activation(saved, B, l).cpu().numpy().astype(np.float64) for l in range(L + 1)]
     g_out = (2.0 / B) * (xh.reshape(B, -1).cpu().numpy().astype(np.float64) - case.x)
     g, gy = net.backward(_t(g_out).reshape(B, case.n1, case.n2), saved, params, want_gy=want_gy)
     torch.cuda.synchronize()
     gpu = (float("nan"), [w.cpu().numpy() for w in g.w], [b.cpu().numpy() for b in g.b],
            gy.cpu().numpy() if gy is not None else None)
     H = oracle.backward_acts(case.oracle_net(), case.phi.T, case.w, case.y,
-                             [[acts[l][b] for l in range(4)] for b in range(B)], g_out, want_gy=want_gy)
-    gb = [oracle.crop_full(H.b[l], 11) if case.bias_per_pixel else H.b[l] for l in range(3)]
+                             [[acts[l][b] for l in range(L + 1)] for b in range(B)], g_out, want_gy=want_gy)
+    gb = [oracle.crop_full(H.b[l], case.k[l]) if case.bias_per_pixel else H.b[l] for l in range(L)]
     net.free()
-    return gpu, (float("nan"), H.w, gb, H.y)
+    return gpu, (float("nan"), H.w, gb, H.y), acts
 
 
-def _check_e2e_bf16(gpu, ref, label):
+def _flip_fraction(case, acts, idx=None):
+    """Largest fraction, over the hidden layers, of units active (> 0) in one forward
+    state and not in the other: the GPU's (acts) against the FP64 oracle's."""
+    import oracle
+    y = case.y if idx is None else case.y[idx]
+    _, ref = oracle.forward(case.oracle_net(), case.phi.T, case.w, case.oracle_bias(), y, return_acts=True)
+    f = 0.0
+    for l in range(1, len(case.k)):
+        gpu_on = acts[l] > 0
+        orc_on = np.stack([r[l] for r in ref]) > 0
+        f = max(f, float(np.mean(gpu_on != orc_on)))
+    return f
+
+
+def _check_e2e(gpu, ref, f, tol, label):
+    """End-to-end gradients against the oracle's own forward state: per tensor
+    tol + 3 sqrt(f) (f from _flip_fraction); the loss, a sum of squares that does
+    not jump at a kink, within the forward pass's own tolerance."""
     lg, wg, bg, yg = gpu
     lr, wr, br, yr = ref
-    errs = {"loss": abs(lg - lr) / abs(lr)}
+    errs = {}
     for l in range(len(wr)):
         errs[f"w{l}"] = _rel(wg[l], wr[l])
         errs[f"b{l}"] = _rel(bg[l], br[l])
-    if yr is not None:
+    if yr is not None and yg is not None:
         errs["y"] = _rel(yg, yr)
-    print(label, "end-to-end vs FP64:", " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= E2E_BF16[k[0] if k != "loss" else "loss"]}
+    bound = tol + 3.0 * np.sqrt(f)
+    lerr = abs(lg - lr) / abs(lr)
+    print(label, f"end-to-end vs FP64 (flipped units {f:.2e}, bound {bound:.2e}): loss={lerr:.2e}",
+          " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
+    bad = {k: v for k, v in errs.items() if not v <= bound}
     assert not bad, (label, bad)
+    assert lerr <= (2e-2 if tol >= 1e-3 else 1e-5), (label, lerr)
 
 
 @pytest.mark.parametrize("prec", ["f32", "bf16"])
@@ -131,14 +156,15 @@ def test_loss_grad_paper_net_ragged(dsi, prec, bias_per_pixel):
     case = make_case(40, 48, 500, 3, cfg_id=21, bias_per_pixel=bias_per_pixel, bias_std=0.05)
     label = f"{prec} bias_pp={bias_per_pixel}"
     if prec == "bf16":
-        gpu, ref = _gpu_grads_same_state(ctx, case, want_gy=True)
+        gpu, ref, acts = _gpu_grads_same_state(ctx, case, want_gy=True)
         _check_same_state(gpu, ref, label)
-        _check_e2e_bf16(_gpu_grads(ctx, case, "bf16", want_gy=True), _oracle_grads(case, want_gy=True), label)
+        _check_e2e(_gpu_grads(ctx, case, "bf16", want_gy=True), _oracle_grads(case, want_gy=True),
+                   _flip_fraction(case, acts), GTOL["bf16"], label)
     else:
         _check(_gpu_grads(ctx, case, prec, want_gy=True), _oracle_grads(case, want_gy=True), GTOL[prec], label)
 
 
-def _check_same_state(gpu, ref, label):
+def _check_same_state(gpu, ref, label, tol=GTOL["bf16"]):
     _, wg, bg, yg = gpu
     _, wr, br, yr = ref
     errs = {}
@@ -148,7 +174,7 @@ def _check_same_state(gpu, ref, label):
     if yr is not None:
         errs["y"] = _rel(yg, yr)
     print(label, "same forward state:", " ".join(f"{k}={v:.2e}" for k, v in errs.items()))
-    bad = {k: v for k, v in errs.items() if not v <= GTOL["bf16"]}
+    bad = {k: v for k, v in errs.items() if not v <= tol}
     assert not bad, (label, bad)
 
 
@@ -158,9 +184,10 @@ def test_loss_grad_relu_last_and_wide_image(dsi, prec):
     P, ctx = dsi
     case = make_case(20, 80, 333, 2, cfg_id=22, relu_last=True, bias_std=0.1)
     if prec == "bf16":
-        gpu, ref = _gpu_grads_same_state(ctx, case, want_gy=True)
+        gpu, ref, acts = _gpu_grads_same_state(ctx, case, want_gy=True)
         _check_same_state(gpu, ref, "bf16 relu_last")
-        _check_e2e_bf16(_gpu_grads(ctx, case, "bf16"), _oracle_grads(case), "bf16 relu_last")
+        _check_e2e(_gpu_grads(ctx, case, "bf16"), _oracle_grads(case), _flip_fraction(case, acts), GTOL["bf16"],
+                   "bf16 relu_last")
     else:
         _check(_gpu_grads(ctx, case, prec), _oracle_grads(case), GTOL[prec], f"{prec} relu_last")
 
@@ -234,11 +261,14 @@ def test_full_size_batch_gradient_is_sum_of_subbatches(dsi):
         assert _rel(acc_b[l].cpu().numpy(), g.b[l].cpu().numpy()) <= 1e-4
     # and the first sub-batch against the oracle at full image size
     case2 = make_case(64, 64, 1024, 128, cfg_id=25, bias_std=0.02)
-    ref = _oracle_grads(case2, idx=np.arange(2))
+    idx = np.arange(2)
+    ref = _oracle_grads(case2, idx=idx)
     y2, x2 = y[:2].contiguous(), x[:2].contiguous()
     l2, g2, _ = net.loss_grad(y2, x2, params)
-    _check_e2e_bf16((l2.item(), [w.cpu().numpy() for w in g2.w], [b.cpu().numpy() for b in g2.b], None), ref,
-                    "64x64 bf16 sub-batch")
+    _, saved2 = net.forward_train(y2)
+    acts2 = [net.saved_activation(saved2, 2, l).cpu().numpy().astype(np.float64) for l in range(4)]
+    _check_e2e((l2.item(), [w.cpu().numpy() for w in g2.w], [b.cpu().numpy() for b in g2.b], None), ref,
+               _flip_fraction(case2, acts2, idx), GTOL["bf16"], "64x64 bf16 sub-batch")
     net.free()
 
 
@@ -311,3 +341,32 @@ def test_metrics_match_oracle(dsi):
     np.testing.assert_allclose(out[:, 1], oracle.psnr(xh, x), rtol=1e-6)
     np.testing.assert_allclose(out[:, 2], oracle.relerr(xh, x), rtol=1e-6)
     np.testing.assert_array_equal(out[:, 3], oracle.success(xh, x))
+
+
+def test_loss_grad_bf16_width_not_multiple_of_8(dsi):
+    """45x50 images, batch 3: BF16 training at a width that is not a multiple of 8 takes
+    the blocked conv2 weight-gradient kernel (which stages channel-blocked data itself)
+    and conv layer 1's unaligned halo staging; same-state gate 2e-2 per tensor."""
+    P, ctx = dsi
+    case = make_case(45, 50, 700, 3, cfg_id=29, bias_std=0.05)
+    gpu, ref, acts = _gpu_grads_same_state(ctx, case, want_gy=True)
+    _check_same_state(gpu, ref, "bf16 45x50")
+    _check_e2e(_gpu_grads(ctx, case, "bf16", want_gy=True), _oracle_grads(case, want_gy=True),
+               _flip_fraction(case, acts), GTOL["bf16"], "bf16 45x50")
+
+
+@pytest.mark.parametrize("prec,M", [("bf16", 1024), ("bf16", 410), ("f32", 410)])
+def test_loss_grad_training_shape(dsi, prec, M):
+    """The training configuration: 64x64 images, batch 128, M/N = 0.25 (M = 1024) and
+    0.10 (M = 410).  Every gradient tensor of the backward kernels against the oracle's
+    FP64 backpropagation on the GPU's own forward state (BF16 2e-2, FP32 1e-5 per
+    tensor), and end to end against the oracle's own forward state within the
+    tolerance plus 3 sqrt(flipped fraction)."""
+    P, ctx = dsi
+    case = make_case(64, 64, M, 128, cfg_id=30 + (M == 410), bias_std=0.02)
+    gpu, ref, acts = _gpu_grads_same_state(ctx, case, want_gy=True, prec=prec)
+    _check_same_state(gpu, ref, f"{prec} 64x64 B=128 M={M}", tol=GTOL[prec])
+    f = _flip_fraction(case, acts)
+    del acts
+    _check_e2e(_gpu_grads(ctx, case, prec, want_gy=True), _oracle_grads(case, want_gy=True), f, GTOL[prec],
+               f"{prec} 64x64 B=128 M={M}")
