@@ -219,35 +219,32 @@ def sweep_leg(ctx, P, torch, n_test=2000, train_steps=2000, log=None):
         if log:
             log(f"sweep M/N {r:.2f}: success {m[:, 3].mean():.3f}, PSNR {m[:, 1].mean():.2f} dB, "
                 f"{ms1 * 1e3:.0f} us per image alone")
-        data[f"{r:.2f}"] = {"phi": phi, "y": yt[:16].cpu().numpy().astype(np.float64)}
+        data[f"{r:.2f}"] = {"phi": phi, "y": yt[:100].cpu().numpy().astype(np.float64)}
         net.free()
     out["workload"] = (f"32x32 piecewise-smooth images, Gaussian Phi per ratio, network trained "
                        f"{train_steps} Adam steps (lr 3e-4, batch 128) per ratio, {n_test} test images")
-    return out, {"x": xtest[:16], "ratios": data}
+    return out, {"x": xtest[:100], "ratios": data}
 
 
-def cpu_sweep(sw, n_img=16, threads=16):
+def cpu_sweep(sw, n_img=100):
     """ISTA-DCT (the classical sparsity-regularised solver) on the first n_img test images
-    of every ratio of the sweep, images in parallel threads: success rate, PSNR, time."""
+    of every ratio of the sweep (one batched oracle call per ratio, its threads over the
+    host's cores): success rate, PSNR, time per image."""
     import oracle
-    from concurrent.futures import ThreadPoolExecutor
     out = {}
     x = sw["x"][:n_img]
     for key, d in sw["ratios"].items():
-        def one(i):
-            t0 = time.perf_counter()
-            xi, _, _ = oracle.ista_dct(d["phi"], d["y"][i], SWEEP_N, SWEEP_N)
-            return xi, time.perf_counter() - t0
-        with ThreadPoolExecutor(max_workers=threads) as ex:
-            res = list(ex.map(one, range(n_img)))
-        xh = np.stack([r[0] for r in res])
+        t0 = time.perf_counter()
+        xh, _, _ = oracle.ista_dct_batch(d["phi"], d["y"][:n_img], SWEEP_N, SWEEP_N)
+        dt = time.perf_counter() - t0
         out[key] = {"success_rate": float(oracle.success(xh, x).mean()),
                     "psnr_mean_db": float(oracle.psnr(xh, x).mean()),
-                    "seconds_per_image": float(np.mean([r[1] for r in res])), "images": n_img}
+                    "seconds_per_image": dt / n_img, "images": n_img,
+                    "note": "wall time of the batch on the host's threads, divided by the images"}
     return out
 
 
-def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=3e-4, pool=4096):
+def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=3e-4, pool=4096, Mx=M):
     """Adam training of the network (Sec. 4: MSE loss, backpropagation) on a pool of
     synthetic piecewise-smooth 64x64 images (a different seed from the benchmark
     batch), BF16 compute with FP32 master weights, through dsi_train_step.
@@ -257,7 +254,7 @@ def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=3e-4, pool=40
     xs = synth.piecewise_smooth_images(pool, N1, N2, cfg_id=3, stream=11).reshape(pool, -1)
     xd = torch.tensor(xs, dtype=torch.float32, device=dev)
     yd = ctx.measure(torch.tensor(np.ascontiguousarray(phi), dtype=torch.float32, device=dev), xd)
-    net = ctx.prepare(N1, N2, M, params, prec="bf16")
+    net = ctx.prepare(N1, N2, Mx, params, prec="bf16")
     net.reserve(batch, train=True)
     opt = P.AdamState.zeros_like(params)
     g = synth.rng(3, 12)
@@ -275,8 +272,62 @@ def train_network(ctx, P, torch, phi, params, steps, batch=128, lr=3e-4, pool=40
     ms = ev0.elapsed_time(ev1) / max(steps, 1)
     net.free()
     L = [float(v.item()) for v in losses]
-    return {"steps": steps, "batch": batch, "lr": lr, "ms_per_step": ms, "images_per_s": batch / (ms / 1e3),
+    return {"steps": steps, "batch": batch, "lr": lr, "M": Mx, "ms_per_step": ms, "images_per_s": batch / (ms / 1e3),
             "loss_first": L[0], "loss_last": L[-1], "precision": "bf16 compute, fp32 master weights"}
+
+
+T3_M = 410          # M/N = 0.10 at 64 x 64 (Sec. 5, Table 3)
+T3_SNR_DB = 20.0
+
+
+def table3_leg(ctx, P, torch, train_steps, n_test=256):
+    """Noisy measurements (Sec. 5, Table 3 analogue) at 64 x 64, M/N = 0.10 (M = 410):
+    a network trained from He-init on its own Phi (noiseless training data, BF16,
+    Adam), then mean PSNR over n_test fresh images from noiseless y = Phi x and from
+    y = Phi x + e at 20 dB SNR per measurement vector (dsi_measure_noisy, the noise
+    draw e seeded)."""
+    import synth
+    dev = "cuda:0"
+    N = N1 * N2
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    phi = synth.make_phi(T3_M, N, cfg_id=6)
+    prm = synth.he_init(synth.PAPER_ARCH, N1, N2, bias_per_pixel=True, cfg_id=6)
+    params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+    train = train_network(ctx, P, torch, phi, params, train_steps, Mx=T3_M)
+    x = synth.piecewise_smooth_images(n_test, N1, N2, cfg_id=6).reshape(n_test, -1)
+    e = synth.normal_values((n_test, T3_M), 1.0, 6, 7)
+    phi_d, x_d = t(phi), t(x)
+    ys = {"noiseless": ctx.measure(phi_d, x_d), "snr20db": ctx.measure_noisy(phi_d, x_d, t(e), T3_SNR_DB)}
+    net = ctx.prepare(N1, N2, T3_M, params, prec="bf16")
+    out = {"workload": f"64x64 piecewise-smooth images, M={T3_M} (M/N=0.10), network trained {train_steps} "
+                       f"Adam steps on noiseless measurements; {n_test} test images, noise at "
+                       f"{T3_SNR_DB:.0f} dB SNR per measurement vector",
+           "training": train}
+    host = {"phi": phi, "x": x}
+    for k, y in ys.items():
+        xh = net.recover(y)
+        m = ctx.metrics(xh.reshape(n_test, -1), x_d).cpu().numpy()
+        out[k] = {"network_psnr_mean_db": float(m[:, 1].mean()), "network_success_rate": float(m[:, 3].mean())}
+        host[k] = y.cpu().numpy().astype(np.float64)
+    out["psnr_drop_db_network"] = out["noiseless"]["network_psnr_mean_db"] - out["snr20db"]["network_psnr_mean_db"]
+    net.free()
+    return out, host
+
+
+def cpu_table3(t3, n_img=32):
+    """ISTA-DCT on the first n_img test images of the noisy-measurement leg, from the
+    noiseless and from the 20 dB measurements: mean PSNR (and time per image)."""
+    import oracle
+    out = {"images": n_img}
+    x = t3["x"][:n_img]
+    for k in ("noiseless", "snr20db"):
+        t0 = time.perf_counter()
+        xh, _, _ = oracle.ista_dct_batch(t3["phi"], t3[k][:n_img], N1, N2)
+        dt = time.perf_counter() - t0
+        out[k] = {"ista_psnr_mean_db": float(oracle.psnr(xh, x).mean()),
+                  "ista_success_rate": float(oracle.success(xh, x).mean()), "seconds": dt}
+    out["psnr_drop_db_ista"] = out["noiseless"]["ista_psnr_mean_db"] - out["snr20db"]["ista_psnr_mean_db"]
+    return out
 
 
 def calibration_y(ctx, P, torch, phi, B=64):
@@ -367,9 +418,11 @@ def main():
     ap.add_argument("--serve-qps", type=str, default="2000,8000,64000",
                     help="offered loads (requests/s); the highest should exceed capacity")
     ap.add_argument("--no-extra", action="store_true", help="skip the 128x128 FP8 and 32x32 legs")
-    ap.add_argument("--sweep", action="store_true",
-                    help="also run the M/N sweep (32x32: trained networks per ratio, 2000 test images, "
-                         "ISTA-DCT on 16 of them); adds a few minutes")
+    ap.add_argument("--no-sweep", action="store_true",
+                    help="skip the M/N sweep (32x32: a trained network per ratio, 2000 test images, "
+                         "ISTA-DCT on 100 of them)")
+    ap.add_argument("--no-noise", action="store_true",
+                    help="skip the noisy-measurement leg (64x64, M/N = 0.10, 20 dB; ISTA-DCT on 32 images)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -409,8 +462,13 @@ def main():
         net.free()
 
     sw = sw_data = None
-    if args.sweep:
+    if not args.no_sweep:
         sw, sw_data = sweep_leg(ctx, P, torch, log=lambda m: print(m, file=sys.stderr, flush=True))
+    t3 = t3_data = None
+    if not args.no_noise:
+        t3, t3_data = table3_leg(ctx, P, torch, max(args.train_steps, 500))
+        print(f"noisy measurements: network PSNR {t3['noiseless']['network_psnr_mean_db']:.2f} -> "
+              f"{t3['snr20db']['network_psnr_mean_db']:.2f} dB", file=sys.stderr, flush=True)
     c4 = c4_data = c1 = c1_data = None
     if not args.no_extra:
         c4, c4_data = c4_leg(ctx, P, torch, 20, 3)
@@ -460,6 +518,7 @@ def main():
         "c4_128x128": c4,
         "c1_32x32": c1,
         "sweep_mn": sw,
+        "noisy_measurements": t3,
     }
     if not args.no_cpu:
         y_host = y.cpu().numpy().astype(np.float64)
@@ -469,6 +528,10 @@ def main():
         out["accuracy_vs_fp64_on_sample"] = acc
         if sw_data is not None:
             out["sweep_mn_ista_dct"] = cpu_sweep(sw_data)
+            print("sweep: ISTA-DCT done", file=sys.stderr, flush=True)
+        if t3_data is not None:
+            out["noisy_measurements"]["ista_dct"] = cpu_table3(t3_data)
+            print("noisy measurements: ISTA-DCT done", file=sys.stderr, flush=True)
         if c1 is not None and "ista_dct" in cb:
             out["c1_32x32"]["ista_over_network_time_per_image"] = (
                 cb["ista_dct"]["seconds_per_image"] / (c1["batch8"]["us_per_image"] * 1e-6))
