@@ -199,24 +199,29 @@ __global__ __launch_bounds__(256) void gemm_frag_kernel(const T *__restrict__ Xp
   for (int r = 0; r < 16; ++r) acc[r] = 0.0f;
   Frag8<T> fx[PF], fw[PF];
 #pragma unroll
-  for (int p = 0; p < PF; ++p)
-    if (p < KS) {
-      fx[p] = frag_load<T>(px + (long)p * 64 * FE);
-      fw[p] = frag_load<T>(pw + (long)p * 64 * FE);
-    }
-  for (int k = 0; k < KS; k += PF) {
+  for (int p = 0; p < PF; ++p) {
+    const int kp = min(p, KS - 1);
+    fx[p] = frag_load<T>(px + (long)kp * 64 * FE);
+    fw[p] = frag_load<T>(pw + (long)kp * 64 * FE);
+  }
+  // Full iterations of PF k-steps issue their loads unconditionally (past the end, of the
+  // last k-step again), so each iteration has the same loads in flight and the wait before
+  // a k-step's MFMA counts only the loads issued after its own (a conditional load or MFMA
+  // would make the compiler wait for every load in flight at each iteration).  The last
+  // KS mod PF k-steps were loaded by the last full iteration (or the prologue).
+  const int KF = KS / PF * PF;
+  for (int k = 0; k < KF; k += PF) {
 #pragma unroll
     for (int p = 0; p < PF; ++p) {
-      if (k + p < KS) {
-        fx[p].mma(fw[p], acc);
-        const int kn = k + p + PF;
-        if (kn < KS) {
-          fx[p] = frag_load<T>(px + (long)kn * 64 * FE);
-          fw[p] = frag_load<T>(pw + (long)kn * 64 * FE);
-        }
-      }
+      fx[p].mma(fw[p], acc);
+      const int kn = min(k + p + PF, KS - 1);
+      fx[p] = frag_load<T>(px + (long)kn * 64 * FE);
+      fw[p] = frag_load<T>(pw + (long)kn * 64 * FE);
     }
   }
+#pragma unroll
+  for (int p = 0; p < PF; ++p)
+    if (p < KS - KF) fx[p].mma(fw[p], acc);
   const int o = ot * 32 + (lane & 31);
   if (o >= O) return;
 #pragma unroll
