@@ -107,6 +107,16 @@ typedef struct {
 dsi_status dsi_create(dsi_ctx **out, int device);
 /* Destroy a context and its workspace.  Waits for the device to go idle. */
 dsi_status dsi_destroy(dsi_ctx *ctx);
+/* Give the context a caller-owned device workspace of `bytes` bytes (16-byte
+ * aligned) instead of the one it allocates and grows itself (which is freed
+ * here).  The context never frees or grows caller memory: a later call that
+ * needs more than `bytes` (dsi_workspace_size and the training sizes) fails
+ * with DSI_E_NOMEM before any launch.  ws = NULL returns to a library-owned
+ * workspace, allocated on demand.  The memory must stay valid while the
+ * context uses it; calls on the context then use only its first bytes that
+ * they need, so a caller may keep other data in its tail (a serving loop
+ * keeps its staging buffers there). */
+dsi_status dsi_set_workspace(dsi_ctx *ctx, void *ws, size_t bytes);
 /* Thread-local message of the last error on this thread ("" if none). */
 const char *dsi_last_error(void);
 /* Library version string. */

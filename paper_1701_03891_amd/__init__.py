@@ -153,6 +153,16 @@ class Context:
         except Exception:
             pass
 
+    def set_workspace(self, buf):
+        """Use the device tensor buf (uint8, contiguous) as the context's workspace (None:
+        back to a library-owned one).  The caller keeps buf alive while it is in use."""
+        if buf is None:
+            _lib.dsi_set_workspace(self.h, None, 0)
+            self._ws_ref = None
+            return
+        _lib.dsi_set_workspace(self.h, _ptr(buf), buf.numel() * buf.element_size())
+        self._ws_ref = buf
+
     def set_recompute_budget(self, nbytes: int):
         """Workspace bytes one chunk of recompute-mode training may use (0: whole batch)."""
         _lib.dsi_set_recompute_budget(self.h, int(nbytes))

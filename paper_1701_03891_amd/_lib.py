@@ -29,7 +29,7 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
            "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation", "dsi_net_calibrate",
            "dsi_net_get_scales", "dsi_measure_noisy", "dsi_recover_noalloc",
-           "dsi_set_recompute_budget"]
+           "dsi_set_recompute_budget", "dsi_set_workspace"]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20     # DSI_NOALLOC_SCRATCH_BYTES
 
@@ -93,6 +93,7 @@ def lib() -> ctypes.CDLL:
         "dsi_forward_train": (st, [P, P, P, P, i, P, z, i, P]),
         "dsi_backward": (st, [P, P, P, P, z, i, i, ctypes.POINTER(Params), P, P]),
         "dsi_set_recompute_budget": (st, [P, z]),
+        "dsi_set_workspace": (st, [P, P, z]),
         "dsi_loss_grad": (st, [P, P, P, P, i, ctypes.POINTER(Params), P, P, P]),
         "dsi_train_step": (st, [P, P, ctypes.POINTER(Params), ctypes.POINTER(Adam), P, P, i,
                                 ctypes.c_float, P, P]),
@@ -187,6 +188,10 @@ def dsi_forward_train(ctx, net, y, xhat, B, saved, saved_bytes, recompute, strea
 
 def dsi_backward(ctx, net, gxhat, saved, saved_bytes, recompute, B, grads: Params, gy, stream):
     call("dsi_backward", ctx, net, gxhat, saved, saved_bytes, int(recompute), B, ctypes.byref(grads), gy, stream)
+
+
+def dsi_set_workspace(ctx, ws, nbytes):
+    call("dsi_set_workspace", ctx, ws, int(nbytes))
 
 
 def dsi_set_recompute_budget(ctx, nbytes):

@@ -79,6 +79,7 @@ struct dsi_ctx {
   int device = 0;
   void *ws = nullptr;
   size_t ws_bytes = 0;
+  bool ws_caller = false;    // ws is caller memory (dsi_set_workspace): never grown or freed here
   void *fixed_ws = nullptr;  // device address of the fixed workspace array (dsi_recover_noalloc)
   size_t rc_budget = 0;      // workspace bytes a recompute-mode chunk may use (0: whole batch)
   // stage timing (benchmarking): one set of events per timed forward pass
@@ -228,6 +229,9 @@ template <typename T> T *at(void *base, size_t off) { return reinterpret_cast<T 
 
 dsi_status ensure_ws(dsi_ctx *ctx, size_t bytes) {
   if (bytes <= ctx->ws_bytes) return DSI_OK;
+  if (ctx->ws_caller)
+    return fail(DSI_E_NOMEM, "this call needs %zu workspace bytes; the caller's workspace has %zu", bytes,
+                ctx->ws_bytes);
   if (ctx->ws) {
     HIPCHK(hipDeviceSynchronize());
     HIPCHK(hipFree(ctx->ws));
@@ -549,6 +553,9 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
 }
 
 // --------------------------------------------------------------- backward
+// the FC weight gradient's scratch within a backward scratch area of B images
+float *fc_scratch(const dsi_net &n, int B, void *scratch);
+
 template <typename T>
 dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const Layout &L, int B, const dsi_grads *g,
                           float *gy, void *scratch, hipStream_t s);
@@ -620,7 +627,8 @@ dsi_status backward_impl(dsi_ctx *ctx, const dsi_net *n, const void *gz_last, co
                                                                      d.k[l], s)));
     gz = go;
   }
-  if (d.fc_trainable && g->w_fc) HIPCHK(dsi::fc_wgrad_f32(gz, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, s));
+  if (d.fc_trainable && g->w_fc)
+    HIPCHK(dsi::fc_wgrad_f32(gz, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, fc_scratch(*n, B, scratch), s));
   if (gy) {
     // dy = g_xt W_fc: X = g_xt [B][N], W = W_fc^T [M][N] (fp32, built once)
     if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
@@ -700,7 +708,7 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
     // dL/dx~ = dgrad of layer 1
     HIPCHK((dsi::conv_last<T, 64>(g1, (const T *)n->wp1f, nullptr, 0, 0, gxt, B, H, W, s)));
   }
-  if (want_fc) HIPCHK(dsi::fc_wgrad_f32(gxt, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, s));
+  if (want_fc) HIPCHK(dsi::fc_wgrad_f32(gxt, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, fc_scratch(*n, B, scratch), s));
   if (gy) {
     // dy = g_xt W_fc
     if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
@@ -718,6 +726,20 @@ size_t backward_paper_scratch(const dsi_net &n, int B) {
   return rnd(B * 32 * N * es) + rnd(B * 64 * N * es) + rnd(B * N * 4) + planar + rnd(part * 4);
 }
 
+// scratch of the FC weight gradient (transposed dL/dx~ and y), trainable FC layers only
+size_t fc_scratch_bytes(const dsi_net &n, int B) {
+  return n.d.fc_trainable ? rnd((size_t)n.N * B * 4 + 256) + rnd((size_t)n.d.M * B * 4) : 0;
+}
+
+size_t backward_scratch_bytes(const dsi_net &n, int B);
+
+float *fc_scratch(const dsi_net &n, int B, void *scratch) {
+  const size_t es = n.prec == DSI_F64 ? 8 : 4;
+  const size_t off = backward_scratch_bytes(n, B) - fc_scratch_bytes(n, B) - rnd((size_t)B * n.N * es) -
+                     rnd((size_t)B * 4 * 8) - 256;
+  return at<float>(scratch, off);
+}
+
 size_t backward_scratch_bytes(const dsi_net &n, int B) {
   int cmax = 1;
   for (int l = 0; l <= n.d.L; ++l) cmax = std::max(cmax, n.d.C[l]);
@@ -730,6 +752,7 @@ size_t backward_scratch_bytes(const dsi_net &n, int B) {
     b += rnd(wmax * 8) + rnd((size_t)B * n.d.M * 8);
   }
   if (n.path == PATH_PAPER) b = std::max(b, backward_paper_scratch(n, B));
+  b += fc_scratch_bytes(n, B);      // FC weight gradient
   b += rnd((size_t)B * n.N * es);   // gz of the last layer
   b += rnd((size_t)B * 4 * 8) + 256; // per-image stats + loss
   return b;
@@ -760,9 +783,24 @@ dsi_status dsi_create(dsi_ctx **out, int device) {
   return DSI_OK;
 }
 
+dsi_status dsi_set_workspace(dsi_ctx *ctx, void *ws, size_t bytes) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  if (ws && !aligned16(ws)) return fail(DSI_E_ALIGN, "ws must be 16-byte aligned");
+  if (ws && bytes == 0) return fail(DSI_E_SHAPE, "a caller workspace needs bytes > 0");
+  if (set_device(ctx) != DSI_OK) return DSI_E_HIP;
+  if (ctx->ws && !ctx->ws_caller) {   // the library's own workspace goes
+    HIPCHK(hipDeviceSynchronize());
+    HIPCHK(hipFree(ctx->ws));
+  }
+  ctx->ws = ws;
+  ctx->ws_bytes = ws ? bytes : 0;
+  ctx->ws_caller = ws != nullptr;
+  return DSI_OK;
+}
+
 dsi_status dsi_destroy(dsi_ctx *ctx) {
   if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
-  if (ctx->ws) {
+  if (ctx->ws && !ctx->ws_caller) {
     (void)hipSetDevice(ctx->device);
     (void)hipDeviceSynchronize();
     (void)hipFree(ctx->ws);

@@ -84,7 +84,9 @@ hipError_t image_stats_f64(const double *xh, const float *x, int B, int N, doubl
 hipError_t loss_sum(const double *stats, int B, double *loss, hipStream_t s);
 template <typename TI>
 hipError_t unpack_act(const TI *in, ActView vi, float *out, int B, hipStream_t s);
-hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s);
+// tmp: N * B + M * B floats (+ 64 of alignment) of scratch for the transposed operands
+hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, float *tmp,
+                        hipStream_t s);
 hipError_t fc_wgrad_f64(const double *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s);
 hipError_t add_noise(float *y, const float *e, int B, int M, double snr_db, hipStream_t s);
 hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hipStream_t s);

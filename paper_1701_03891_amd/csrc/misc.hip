@@ -347,10 +347,37 @@ __global__ void fc_wgrad_kernel(const TG *__restrict__ g, const float *__restric
   for (int b = 0; b < B; ++b) s += (Acc)g[(long)b * N + p] * (Acc)y[(long)b * ldy + m];
   dw[idx] = (float)s;
 }
-hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s) {
-  const long n = (long)N * M;
-  if (n > 0) fc_wgrad_kernel<float, float><<<GRID1(n), 0, s>>>(g, y, ldy, B, N, M, dw);
-  return hipGetLastError();
+// out[c][r] = in[r][c] for an R x Cc block of in (row stride ldin); out has row stride R.
+// 32 x 32 tiles through LDS (one padding column: conflict-free column reads).
+__global__ __launch_bounds__(256) void transpose_f32_kernel(const float *__restrict__ in, long ldin, int R, int Cc,
+                                                            float *__restrict__ out) {
+  __shared__ float t[32][33];
+  const int r0 = blockIdx.y * 32, c0 = blockIdx.x * 32, tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int r = r0 + ty + 8 * k, c = c0 + tx;
+    t[ty + 8 * k][tx] = (r < R && c < Cc) ? in[(long)r * ldin + c] : 0.0f;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int c = c0 + ty + 8 * k, r = r0 + tx;
+    if (c < Cc && r < R) out[(long)c * R + r] = t[tx][ty + 8 * k];
+  }
+}
+
+// dW_fc[p][m] = sum_b g[b][p] y[b][m] as the MFMA GEMM C[p][m] = sum_b gT[p][b] yT[m][b]
+// (FP32 operands, FP32 accumulation) after transposing g and y into `tmp`
+// (N * B + M * B floats).
+hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, float *tmp,
+                        hipStream_t s) {
+  if ((long)N * M <= 0 || B <= 0) return hipSuccess;
+  float *gT = tmp, *yT = tmp + (((long)N * B + 63) / 64) * 64;
+  transpose_f32_kernel<<<dim3((N + 31) / 32, (B + 31) / 32), 256, 0, s>>>(g, N, B, N, gT);
+  transpose_f32_kernel<<<dim3((M + 31) / 32, (B + 31) / 32), 256, 0, s>>>(y, ldy, B, M, yT);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  return gemm_nt_f32(gT, B, yT, B, dw, M, N, M, B, B % 16 == 0, s);
 }
 hipError_t fc_wgrad_f64(const double *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s) {
   const long n = (long)N * M;

@@ -10,11 +10,13 @@ context and workspace) is free it forms the next batch:
   * continuous batching: the batch takes every waiting image of that network,
     splitting requests across batches when needed, up to the largest batch
     size ("bucket") the HBM budget admits;
-  * admission: a batch is launched only while the bytes of all batches in
-    flight (workspace + input/output staging of their buckets) plus its own
-    stay within the budget;
-  * execution: every (network, bucket, slot) has a HIP graph captured once
-    around dsi_recover on static staging buffers; a launch copies the batch's
+  * admission: the HBM budget is the device memory for batches, allocated once
+    as one arena per execution slot (the slot's workspace and staging); a batch
+    is formed only in a bucket whose workspace and staging fit an arena, and
+    launched only while the bytes of all batches in flight plus its own stay
+    within the budget;
+  * execution: every admissible (network, bucket, slot) has a HIP graph
+    captured once around dsi_recover on the slot's staging buffers; a launch copies the batch's
     measurement vectors into the staging input, replays the graph on the
     slot's stream and records an event; completion is found by polling the
     events, so batches from different networks overlap on the device.
@@ -141,6 +143,10 @@ class Executor:
     def batch_bytes(self, net: int, bucket: int) -> int:
         raise NotImplementedError
 
+    def admissible(self, net: int, bucket: int) -> bool:
+        """Whether a batch of this bucket can run at all (fits one slot's memory)."""
+        return True
+
     def launch(self, batch: Batch):
         raise NotImplementedError
 
@@ -171,12 +177,13 @@ class Server:
         self.n_finished = 0
         smallest = [executor.batch_bytes(k, self.buckets[0]) for k in range(n_nets)]
         for k, b in enumerate(smallest):
-            if b > self.adm.budget:
+            if b > self.adm.budget or not executor.admissible(k, self.buckets[0]):
                 raise ValueError(f"net {k}: one image needs {b} bytes, over the budget {self.adm.budget}")
 
     def _bucket_for(self, net: int, images: int):
         """Smallest bucket holding `images`, shrunk until it fits the free budget."""
-        fit = [b for b in self.buckets if self.adm.fits(self.ex.batch_bytes(net, b))]
+        fit = [b for b in self.buckets
+               if self.ex.admissible(net, b) and self.adm.fits(self.ex.batch_bytes(net, b))]
         if not fit:
             return None, 0
         cover = [b for b in fit if b >= images]
@@ -286,10 +293,18 @@ class FakeExecutor(Executor):
 
 
 class GraphExecutor(Executor):
-    """libdsi on one GPU: per slot a stream and a context; per (net, bucket, slot) a
-    captured graph over static staging buffers."""
+    """libdsi on one GPU, with every byte a batch uses inside the HBM budget.
 
-    def __init__(self, nets, n_slots=4, buckets=DEFAULT_BUCKETS, device=0):
+    The budget is split into one arena per slot (a HIP stream with its own libdsi
+    context).  An arena is its context's workspace (dsi_set_workspace) and, in its
+    tail, holds the staging buffers of the batch running on the slot, so device
+    memory for batches is allocated once, at exactly the budget.  A (net, bucket)
+    is admissible when its workspace plus staging fits one arena: a smaller budget
+    caps the bucket sizes, and the scheduler never forms a batch that does not fit.
+    Per admissible (net, bucket, slot) one HIP graph is captured around dsi_recover.
+    The prepared networks (the resident weights) are shared by the slots."""
+
+    def __init__(self, nets, n_slots=4, buckets=DEFAULT_BUCKETS, device=0, budget=16 << 30):
         import torch
 
         import paper_1701_03891_amd as P
@@ -298,40 +313,60 @@ class GraphExecutor(Executor):
         self.n_slots = n_slots
         self.buckets = tuple(sorted(buckets))
         self.device = device
+        dev = f"cuda:{device}"
+        self.arena_bytes = (int(budget) // n_slots) // 256 * 256
         self.streams = [torch.cuda.Stream(device) for _ in range(n_slots)]
         self.ctxs = [P.Context(device) for _ in range(n_slots)]
-        self.handles = {}   # (slot, net) -> Net
+        self.arenas = [torch.empty(self.arena_bytes, dtype=torch.uint8, device=dev) for _ in range(n_slots)]
+        for c, a in zip(self.ctxs, self.arenas):
+            c.set_workspace(a)
+        self.handles = [self.ctxs[0].prepare(*shape, params, prec=prec) for shape, params, prec in nets]
+        self.weight_bytes = sum(params.w_fc.numel() * 2 for _, params, _ in nets)   # BF16 W_fc dominates
         self.graphs = {}    # (net, bucket, slot) -> (graph, y_static, x_static)
-        self._bytes = {}
+        self._need = {}     # (net, bucket) -> (workspace bytes, staging bytes)
+        rnd = lambda v: (v + 255) // 256 * 256  # noqa: E731
         for k, (shape, params, prec) in enumerate(nets):
             n1, n2, M = shape
-            for s in range(n_slots):
-                net = self.ctxs[s].prepare(n1, n2, M, params, prec=prec)
-                net.reserve(self.buckets[-1])
-                self.handles[(s, k)] = net
             for b in self.buckets:
-                ws = self.handles[(0, k)].workspace_size(b)
-                self._bytes[(k, b)] = ws + b * (M + n1 * n2) * 4
+                self._need[(k, b)] = (self.handles[k].workspace_size(b), rnd(b * M * 4) + rnd(b * n1 * n2 * 4))
+            if not self.admissible(k, self.buckets[0]):
+                raise ValueError(f"net {k}: a batch of {self.buckets[0]} needs {sum(self._need[(k, self.buckets[0])])} "
+                                 f"bytes, over one slot's arena of {self.arena_bytes}")
         torch.cuda.synchronize(device)
-        # capture
+        # staging views in the arena's tail, then capture
         for k, (shape, params, prec) in enumerate(nets):
             n1, n2, M = shape
+            net = self.handles[k]
             for s in range(n_slots):
-                net = self.handles[(s, k)]
                 for b in self.buckets:
-                    ys = torch.zeros((b, M), dtype=torch.float32, device=f"cuda:{device}")
-                    xs = torch.zeros((b, n1, n2), dtype=torch.float32, device=f"cuda:{device}")
+                    if not self.admissible(k, b):
+                        continue
+                    _, stage = self._need[(k, b)]
+                    tail = self.arenas[s][self.arena_bytes - stage:]
+                    ys = tail[:b * M * 4].view(torch.float32).view(b, M)
+                    xo = rnd(b * M * 4)
+                    xs = tail[xo:xo + b * n1 * n2 * 4].view(torch.float32).view(b, n1, n2)
                     with torch.cuda.stream(self.streams[s]):
-                        net.recover(ys, xs)      # warm-up outside capture
+                        ys.zero_()
+                        self._recover(net, s, ys, xs)      # warm-up outside capture
                     self.streams[s].synchronize()
                     g = torch.cuda.CUDAGraph()
                     with torch.cuda.graph(g, stream=self.streams[s]):
-                        net.recover(ys, xs)
+                        self._recover(net, s, ys, xs)
                     self.graphs[(k, b, s)] = (g, ys, xs)
         torch.cuda.synchronize(device)
 
+    def _recover(self, net, slot, ys, xs):
+        """dsi_recover of a shared network with this slot's context (workspace)."""
+        P = self.P
+        P._lib.dsi_recover(self.ctxs[slot].h, net.h, P._ptr(ys), P._ptr(xs), ys.shape[0],
+                           P._stream(self.device))
+
+    def admissible(self, net, bucket) -> bool:
+        return sum(self._need[(net, bucket)]) <= self.arena_bytes
+
     def batch_bytes(self, net, bucket):
-        return self._bytes[(net, bucket)]
+        return sum(self._need[(net, bucket)])
 
     def launch(self, batch):
         """Stage inputs, replay the graph, hand the outputs back, all on the slot's stream
@@ -358,10 +393,11 @@ class GraphExecutor(Executor):
 
     def close(self):
         self.graphs.clear()
-        for net in self.handles.values():
+        for net in self.handles:
             net.free()
         for c in self.ctxs:
             c.close()
+        self.arenas = []
 
 
 # ------------------------------------------------------------ benchmark driver
@@ -427,15 +463,17 @@ def sweep_serving(qps_list, n_req=10000, slots=4, budget_gib=16.0, buckets=DEFAU
     capacity); with at_fraction set, one more point runs at that fraction of it."""
     import torch
     nets, phis = make_workload(sizes, ratios)
-    ex = GraphExecutor(nets, n_slots=slots, buckets=buckets)
     budget = int(budget_gib * (1 << 30))
+    ex = GraphExecutor(nets, n_slots=slots, buckets=buckets, budget=budget)
     Server(ex, len(nets), buckets, budget).run(make_requests(nets, phis, warmup, max(qps_list), cfg_id=8))
 
     def point(qps, cfg_id=7):
         reqs = make_requests(nets, phis, n_req, qps, cfg_id=cfg_id)
         st = Server(ex, len(nets), buckets, budget).run(reqs)
         torch.cuda.synchronize()
-        st.update({"qps": qps, "slots": slots, "budget_bytes": budget, "nets": len(nets)})
+        st.update({"qps": qps, "slots": slots, "budget_bytes": budget, "nets": len(nets),
+                   "arena_bytes_per_slot": ex.arena_bytes,
+                   "max_bucket_per_net": [max(b for b in buckets if ex.admissible(k, b)) for k in range(len(nets))]})
         del reqs
         if log:
             log(f"serving: {qps:.0f} req/s offered -> {st['images_per_s']:.0f} images/s, "
