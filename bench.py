@@ -404,6 +404,56 @@ def cpu_baseline(phi, x, prm, y_host, xhs, n_img, c4=None, c1=None):
     return out, acc
 
 
+def profile_leg(ctx, P, torch, leg, steps, warmup):
+    """One workload and precision alone (for rocprofv3 runs): prepare, warmup + steps
+    recoveries of one batch, each stage's time from the library's HIP events."""
+    import synth
+    cfg, prec = leg.split(":")
+    if cfg == "train":
+        # training steps (forward, loss, backward, Adam, repack) at 64x64, batch 128, M = 1024
+        phi = synth.make_phi(M, N1 * N2, cfg_id=3)
+        prm = synth.he_init(synth.PAPER_ARCH, N1, N2, bias_per_pixel=True, cfg_id=3)
+        t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda:0")  # noqa: E731
+        params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+        st = train_network(ctx, P, torch, phi, params, warmup + steps, batch=128, pool=1024)
+        print(json.dumps({"profile_leg": leg, "training": st}))
+        return
+    if cfg == "c2":
+        n, Mx, B, cid = N1, M, BATCH, 2
+    elif cfg == "c4":
+        n, Mx, B, cid = 128, 4096, 64, 4
+    else:
+        raise SystemExit(f"unknown profiling leg {leg}")
+    dev = "cuda:0"
+    t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device=dev)  # noqa: E731
+    phi = synth.make_phi(Mx, n * n, cfg_id=cid)
+    x = synth.piecewise_smooth_images(B, n, n, cfg_id=cid).reshape(B, -1)
+    prm = synth.he_init(synth.PAPER_ARCH, n, n, bias_per_pixel=True, cfg_id=cid)
+    params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
+    y = ctx.measure(t(phi), t(x))
+    net = ctx.prepare(n, n, Mx, params, prec=prec)
+    if prec == "fp8":
+        xc = synth.piecewise_smooth_images(32, n, n, cfg_id=900 + cid, stream=synth.STREAM_CALIB).reshape(32, -1)
+        net.calibrate(ctx.measure(t(phi), t(xc)))
+    net.reserve(B)
+    xh = torch.empty((B, n, n), dtype=torch.float32, device=dev)
+    for _ in range(warmup):
+        net.recover(y, xh)
+    torch.cuda.synchronize()
+    from paper_1701_03891_amd import _lib
+    _lib.dsi_stage_times(ctx.h)
+    _lib.dsi_set_stage_timing(ctx.h, 1)
+    for _ in range(steps):
+        net.recover(y, xh)
+    torch.cuda.synchronize()
+    _lib.dsi_set_stage_timing(ctx.h, 0)
+    ms, calls = _lib.dsi_stage_times(ctx.h, 4)
+    print(json.dumps({"profile_leg": leg, "batch": B, "image": [n, n], "M": Mx, "steps": calls,
+                      "stage_ms": dict(zip(["proxy_gemm", "conv1", "conv2", "conv3"],
+                                           [v / max(calls, 1) for v in ms]))}))
+    net.free()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -423,6 +473,11 @@ def main():
                          "ISTA-DCT on 100 of them)")
     ap.add_argument("--no-noise", action="store_true",
                     help="skip the noisy-measurement leg (64x64, M/N = 0.10, 20 dB; ISTA-DCT on 32 images)")
+    ap.add_argument("--profile", type=str, default="",
+                    help="profiling mode: run only one workload leg, c2:bf16 | c2:f32 | c2:fp8 (64x64, "
+                         "B=256) or c4:bf16 | c4:fp8 (128x128, M=4096, B=64), warmup + steps recoveries on "
+                         "He-init weights, or train:bf16 (warmup + steps BF16 training steps, 64x64, B=128), "
+                         "and print its timing (not the benchmark line)")
     ap.add_argument("--copy-mib", type=int, default=0,
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
@@ -442,6 +497,10 @@ def main():
         dst.copy_(src)
         torch.cuda.synchronize()
         del src, dst
+    if args.profile:
+        profile_leg(ctx, P, torch, args.profile, args.steps, args.warmup)
+        ctx.close()
+        return
     phi, x, prm, params, x_d, y = make_inputs(ctx, P, torch)
     N = N1 * N2
     train = None
