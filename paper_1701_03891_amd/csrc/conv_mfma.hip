@@ -899,14 +899,25 @@ __global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__
       wf[u][ks] = frag_zero<bf16>();
       if (n16 < 11) wf[u][ks] = frag_load<bf16>(wt + (n16 * 11 + u) * CIN + 32 * ks + 8 * g);
     }
-  // A operand source: input column j (M index n16), channels 32 ks + 8g .. + 7
+  // A operand source: input column j (M index n16), channels 32 ks + 8g .. + 7.  Rows come
+  // through a buffer descriptor over this image, the lane's column in the vector offset and
+  // the row in the scalar offset.  A vector offset of 2^31 (past the image, which the
+  // launcher keeps under 2^31 bytes) reads as zeros, so rows and columns outside the image
+  // take no branch, every row step issues the same loads, and the wait before a row's MFMAs
+  // counts only the loads issued after it (a conditional load would make the compiler wait
+  // for every load in flight once per pass over the ring).
   const int jc = J0 - 5 + 16 * wave + n16;
-  const bool colok = jc >= 0 && jc < W;
-  const bf16 *src = in + (((long)b * (CIN / 16) + (g >> 1)) * H * W + (colok ? jc : 0)) * 16 + 8 * (g & 1);
+  constexpr unsigned OOB = 0x80000000u;
+  const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16 *>(in + (long)b * CIN * H * W), 0,
+                                                      CIN * H * W * 2, 0x00020000);
+  const unsigned lane_off =
+      jc >= 0 && jc < W ? (unsigned)((((g >> 1) * H * W + jc) * 16 + 8 * (g & 1)) * 2) : OOB;
   auto a_load = [&](int t, int ks) {
     const int r = I0 - 5 + t;
-    Frag8<bf16> f = frag_zero<bf16>();
-    if (colok && r >= 0 && r < H) f = frag_load<bf16>(src + ((long)(2 * ks) * H + r) * W * 16);
+    const bool rok = r >= 0 && r < H;
+    Frag8<bf16> f;
+    const auto v = __builtin_amdgcn_raw_buffer_load_b128(rsrc, rok ? lane_off : OOB, rok ? (2 * ks * H + r) * W * 32 : 0, 0);
+    __builtin_memcpy(&f.v, &v, 16);
     return f;
   };
   Frag8<bf16> aq[11][NKS];
@@ -928,48 +939,60 @@ __global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__
       bs[idx] = i < I1 && j < W ? bias[(long)i * W + j] : 0.0f;
     }
   }
-  for (int t0 = 0; t0 < NR; t0 += 11) {
-    static_for<11>([&](auto kc) {
-      constexpr int k = decltype(kc)::value;
-      const int t = t0 + k;
-      if (t < NR) {
-        // filter row u of input row t reaches output row I0 + t - u: its accumulator is
-        // (k - u) mod 11 (t = k mod 11), and u = 0 starts that row
+  // one input row t in ring slot k = t mod 11; `load` refills the slot with row t + 11
+  auto row = [&](auto kc, int t, bool load) {
+    constexpr int k = decltype(kc)::value;
+    // filter row u of input row t reaches output row I0 + t - u: its accumulator is
+    // (k - u) mod 11, and u = 0 starts that row
 #pragma unroll
-        for (int ks = 0; ks < NKS; ++ks)
+    for (int ks = 0; ks < NKS; ++ks)
 #pragma unroll
-          for (int u = 0; u < 11; ++u) {
-            const int slot = (k - u + 11) % 11;
-            const f32x4 c = (u == 0 && ks == 0) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : acc[slot];
-            acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[k][ks].v, wf[u][ks].v, c, 0, 0, 0);
-          }
-        // the ring slot of row t now takes row t + 11
-        if (t + 11 < NR) {
+      for (int u = 0; u < 11; ++u) {
+        const int slot = (k - u + 11) % 11;
+        const f32x4 c = (u == 0 && ks == 0) ? f32x4{0.0f, 0.0f, 0.0f, 0.0f} : acc[slot];
+        acc[slot] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(aq[k][ks].v, wf[u][ks].v, c, 0, 0, 0);
+      }
+    if (load) {
 #pragma unroll
-          for (int ks = 0; ks < NKS; ++ks) aq[k][ks] = a_load(t + 11, ks);
-        }
-        if (t >= 10) {   // output row I0 + t - 10 is complete in accumulator (k + 1) mod 11
-          constexpr int done = (k + 1) % 11;
-          const int orow = t - 10, grp = orow / RG;
-          float *q = qs[grp & 1][orow - grp * RG];
-          // lane (v = n16, g) holds input columns 16 wave + 4g + e of tap column v
+      for (int ks = 0; ks < NKS; ++ks) aq[k][ks] = a_load(t + 11, ks);
+    }
+    if (t >= 10) {   // output row I0 + t - 10 is complete in accumulator (k + 1) mod 11
+      constexpr int done = (k + 1) % 11;
+      const int orow = t - 10, grp = orow / RG;
+      float *q = qs[grp & 1][orow - grp * RG];
+      // lane (v = n16, g) holds input columns 16 wave + 4g + e of tap column v
 #pragma unroll
-          for (int e = 0; e < 4; ++e) q[(16 * wave + 4 * g + e) * QS + n16] = acc[done][e];
-          // every RG rows (and after the last) the threads add up the group's outputs
-          if (orow - grp * RG == RG - 1 || t == NR - 1) {
-            __syncthreads();
-            const int i = I0 + grp * RG + rg;
-            if (io_ok && i < I1) {
-              const float *qr = qs[grp & 1][rg];
-              float s = bias ? (bias_pp ? bs[(i - I0) * NOUT + jt] : b0) : 0.0f;
+      for (int e = 0; e < 4; ++e) q[(16 * wave + 4 * g + e) * QS + n16] = acc[done][e];
+      // every RG rows (and after the last) the threads add up the group's outputs
+      if (orow - grp * RG == RG - 1 || t == NR - 1) {
+        __syncthreads();
+        const int i = I0 + grp * RG + rg;
+        if (io_ok && i < I1) {
+          const float *qr = qs[grp & 1][rg];
+          float s = bias ? (bias_pp ? bs[(i - I0) * NOUT + jt] : b0) : 0.0f;
 #pragma unroll
-              for (int v = 0; v < 11; ++v) s += qr[(jt + v) * QS + v];
-              out[((long)b * H + i) * W + jo] = relu ? fmaxf(s, 0.0f) : s;
-            }
-          }
+          for (int v = 0; v < 11; ++v) s += qr[(jt + v) * QS + v];
+          out[((long)b * H + i) * W + jo] = relu ? fmaxf(s, 0.0f) : s;
         }
       }
+    }
+  };
+  if constexpr (NKS == 1) {
+    // full passes over the ring load the next pass's rows (past the band's end, unused
+    // ones); the last NR mod 11 rows were loaded by the last full pass
+    const int NF = NR / 11 * 11;
+    for (int t0 = 0; t0 < NF; t0 += 11)
+      static_for<11>([&](auto kc) { row(kc, t0 + decltype(kc)::value, true); });
+    static_for<11>([&](auto kc) {
+      if (NF + decltype(kc)::value < NR) row(kc, NF + decltype(kc)::value, false);
     });
+  } else {
+    // (64 channels: twice the fragments in registers; the one-body walk keeps them there)
+    for (int t0 = 0; t0 < NR; t0 += 11)
+      static_for<11>([&](auto kc) {
+        const int t = t0 + decltype(kc)::value;
+        if (t < NR) row(kc, t, t + 11 < NR);
+      });
   }
 }
 
@@ -1039,6 +1062,7 @@ hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, in
   if constexpr (sizeof(T) == 2) {
     // 5 waves: 80 input columns, 70 output columns per block; bands of 64 output rows
     constexpr int NWV = 5, NOUT = 16 * NWV - 10, RB = 64;
+    if ((long)CIN * H * W * 2 >= (1L << 31)) return hipErrorInvalidValue;   // buffer offsets are 31-bit
     const int col_tiles = (W + NOUT - 1) / NOUT, row_tiles = (H + RB - 1) / RB;
     const long blocks = (long)B * col_tiles * row_tiles;
     if (blocks >= (1L << 31)) return hipErrorInvalidValue;
