@@ -708,7 +708,10 @@ dsi_status backward_paper(const dsi_net *n, const float *gz3, void *sv, const La
     // dL/dx~ = dgrad of layer 1
     HIPCHK((dsi::conv_last<T, 64>(g1, (const T *)n->wp1f, nullptr, 0, 0, gxt, B, H, W, s)));
   }
-  if (want_fc) HIPCHK(dsi::fc_wgrad_f32(gxt, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, fc_scratch(*n, B, scratch), s));
+  if (want_fc) {
+    if constexpr (bf) HIPCHK(dsi::fc_wgrad_bf16(gxt, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, fc_scratch(*n, B, scratch), s));
+    else HIPCHK(dsi::fc_wgrad_f32(gxt, at<float>(sv, L.ykeep), M, B, N, M, g->w_fc, fc_scratch(*n, B, scratch), s));
+  }
   if (gy) {
     // dy = g_xt W_fc
     if (!n->wfcT) return fail(DSI_E_STATE, "internal: W_fc^T missing");
@@ -726,9 +729,12 @@ size_t backward_paper_scratch(const dsi_net &n, int B) {
   return rnd(B * 32 * N * es) + rnd(B * 64 * N * es) + rnd(B * N * 4) + planar + rnd(part * 4);
 }
 
-// scratch of the FC weight gradient (transposed dL/dx~ and y), trainable FC layers only
+// scratch of the FC weight gradient, trainable FC layers only: the transposed dL/dx~ and y in
+// FP32, or (BF16 networks) both packed in fragment order
 size_t fc_scratch_bytes(const dsi_net &n, int B) {
-  return n.d.fc_trainable ? rnd((size_t)n.N * B * 4 + 256) + rnd((size_t)n.d.M * B * 4) : 0;
+  if (!n.d.fc_trainable) return 0;
+  return std::max(rnd((size_t)n.N * B * 4 + 256) + rnd((size_t)n.d.M * B * 4),
+                  rnd(dsi::fc_wgrad_bf16_scratch(B, n.N, n.d.M)));
 }
 
 size_t backward_scratch_bytes(const dsi_net &n, int B);

@@ -183,9 +183,9 @@ hipError_t gemm_nt_fp8(const u8 *X, long ldx, const u8 *W, long ldw, bf16 *C, lo
 // (bt, ot) and its k-step ks reads the contiguous fragments Xp[bt][ks] and
 // Wp[ot][ks] (64 lanes x FE elements each), so every load instruction is one
 // coalesced 1 KiB (bf16) or 2 KiB (FP8) run.  PF k-steps are kept in flight.
-template <typename T>
+template <typename T, typename TO>
 __global__ __launch_bounds__(256) void gemm_frag_kernel(const T *__restrict__ Xp, const T *__restrict__ Wp,
-                                                        bf16 *__restrict__ C, long ldc, int Bn, int O, int KS,
+                                                        TO *__restrict__ C, long ldc, int Bn, int O, int KS,
                                                         float scale) {
   constexpr int FE = sizeof(T) == 1 ? 32 : 8;
   constexpr int PF = sizeof(T) == 1 ? 8 : 16;   // k-steps in flight: the loads are latency-bound
@@ -227,21 +227,28 @@ __global__ __launch_bounds__(256) void gemm_frag_kernel(const T *__restrict__ Xp
 #pragma unroll
   for (int r = 0; r < 16; ++r) {
     const int b = bt * 32 + mfma_row(lane, r);
-    if (b < Bn) C[(long)b * ldc + o] = (bf16)(acc[r] * scale);
+    if (b < Bn) C[(long)b * ldc + o] = (TO)(acc[r] * scale);
   }
 }
 
 hipError_t gemm_frag_bf16(const bf16 *Xp, const bf16 *Wp, bf16 *C, long ldc, int Bn, int O, int KS, hipStream_t s) {
   if (Bn <= 0 || O <= 0) return hipSuccess;
   dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
-  gemm_frag_kernel<bf16><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, 1.0f);
+  gemm_frag_kernel<bf16, bf16><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, 1.0f);
+  return hipGetLastError();
+}
+hipError_t gemm_frag_bf16_f32(const bf16 *Xp, const bf16 *Wp, float *C, long ldc, int Bn, int O, int KS,
+                              hipStream_t s) {
+  if (Bn <= 0 || O <= 0) return hipSuccess;
+  dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
+  gemm_frag_kernel<bf16, float><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, 1.0f);
   return hipGetLastError();
 }
 hipError_t gemm_frag_fp8(const u8 *Xp, const u8 *Wp, bf16 *C, long ldc, int Bn, int O, int KS, float scale,
                          hipStream_t s) {
   if (Bn <= 0 || O <= 0) return hipSuccess;
   dim3 grid(ceil_div(O, 64), ceil_div(Bn, 64));
-  gemm_frag_kernel<u8><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, scale);
+  gemm_frag_kernel<u8, bf16><<<grid, 256, 0, s>>>(Xp, Wp, C, ldc, Bn, O, KS, scale);
   return hipGetLastError();
 }
 

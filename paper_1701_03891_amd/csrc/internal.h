@@ -88,6 +88,11 @@ hipError_t unpack_act(const TI *in, ActView vi, float *out, int B, hipStream_t s
 hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, float *tmp,
                         hipStream_t s);
 hipError_t fc_wgrad_f64(const double *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s);
+// BF16 networks: dW_fc = g^T y on the BF16 matrix cores (FP32 accumulation and output); tmp holds
+// fc_wgrad_bf16_scratch(B, N, M) bytes (256-byte aligned)
+size_t fc_wgrad_bf16_scratch(int B, int N, int M);
+hipError_t fc_wgrad_bf16(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, void *tmp,
+                         hipStream_t s);
 hipError_t add_noise(float *y, const float *e, int B, int M, double snr_db, hipStream_t s);
 hipError_t relu_mask_f32(const float *g, const float *a, float *out, long n, hipStream_t s);
 hipError_t relu_mask_f64(const float *g, const double *a, double *out, long n, hipStream_t s);
@@ -131,12 +136,17 @@ hipError_t amax_f32(const float *x, long n, unsigned *out, hipStream_t s);
 hipError_t amax_bf16(const __bf16 *x, long n, unsigned *out, hipStream_t s);
 hipError_t quant_rows(const float *in, unsigned char *out, int B, int M, int Mpad, float inv_scale, hipStream_t s);
 hipError_t pack_frag_bf16(const float *z, long ld, int R, int K, int Rp, int Kp, __bf16 *out, hipStream_t s);
+// the same for a transposed source: element (r, k) at z[k ld + r]
+hipError_t pack_frag_bf16_t(const float *z, long ld, int R, int K, int Rp, int Kp, __bf16 *out, hipStream_t s);
 hipError_t pack_frag_fp8(const float *z, long ld, int R, int K, int Rp, int Kp, float inv_scale, unsigned char *out,
                          hipStream_t s);
 hipError_t fc_transpose(const void *w, int frag, int N, int M, int Mpad, float *wT, hipStream_t s);
 // C[b][o] = scale * sum_k X[b][k] W[o][k], both operands in MFMA fragment order (pack_frag_*),
 // KS k-steps; C [Bn][ldc] bf16
 hipError_t gemm_frag_bf16(const __bf16 *Xp, const __bf16 *Wp, __bf16 *C, long ldc, int Bn, int O, int KS, hipStream_t s);
+// the same GEMM with an FP32 output (the trainable FC's weight gradient)
+hipError_t gemm_frag_bf16_f32(const __bf16 *Xp, const __bf16 *Wp, float *C, long ldc, int Bn, int O, int KS,
+                              hipStream_t s);
 hipError_t gemm_frag_fp8(const unsigned char *Xp, const unsigned char *Wp, __bf16 *C, long ldc, int Bn, int O, int KS,
                          float scale, hipStream_t s);
 hipError_t pack_mid_fp8(const float *w, unsigned char *out, float inv_scale, hipStream_t s);

@@ -243,31 +243,69 @@ hipError_t amax_bf16(const bf16 *x, long n, unsigned *out, hipStream_t s) {
 // scaled by `scale`, zero beyond R or K.  A wave then reads one fragment as one
 // contiguous 64 * FE-element run.  Rp (multiple of 32) and Kp (multiple of 2 FE)
 // are the padded extents.  FE = 8: bf16 (RNE); FE = 32: FP8 e4m3 codes.
-template <typename TD, int FE>
-__global__ void pack_frag_kernel(const float *__restrict__ z, long ld, int R, int K, int Rp, int Kp, float scale,
-                                 TD *__restrict__ out) {
-  const long idx = (long)blockIdx.x * 256 + threadIdx.x;
-  if (idx >= (long)Rp * Kp) return;
-  const int e = (int)(idx % FE);
-  long q = idx / FE;
-  const int l = (int)(q % 64);
-  q /= 64;
-  const int KS = Kp / (2 * FE);
-  const int ks = (int)(q % KS), rt = (int)(q / KS);
-  const int r = rt * 32 + (l & 31), k = ks * 2 * FE + FE * (l >> 5) + e;
-  const float v = (r < R && k < K) ? z[(long)r * ld + k] * scale : 0.0f;
-  if constexpr (FE == 8) out[idx] = from_f32<bf16>(v);
-  else out[idx] = f32_to_e4m3(v);
+template <typename TD, int FE, bool TRANS>
+__global__ __launch_bounds__(256) void pack_frag_kernel(const float *__restrict__ z, long ld, int R, int K, int Rp,
+                                                        int Kp, float scale, TD *__restrict__ out) {
+  // A block converts a 32-row x 64-column tile: the loads of a wave read 64 consecutive
+  // elements of one row (TRANS: element (r, k) is z[k ld + r], and a wave reads 32
+  // consecutive r of two k), the tile passes through LDS (rows padded by 16 bytes against
+  // bank conflicts), and each thread then writes whole lane fragments (FE elements, 16 or
+  // 32 bytes), 64 lanes of one k-step being one contiguous run.
+  constexpr int TC = 64, PAD = 16 / (int)sizeof(TD), NKS = TC / (2 * FE);
+  __shared__ __attribute__((aligned(16))) TD t[32][TC + PAD];
+  const int tid = threadIdx.x, kb = blockIdx.x * TC, rt = blockIdx.y;
+  // every load is issued before any is used (clamped into the matrix; the elements past R
+  // or K are replaced by zero afterwards), so they share one round trip
+  constexpr int NL = 32 * TC / 256;
+  float v[NL];
+  auto rc = [&](int e, int &row, int &col) {
+    row = TRANS ? e % 32 : e / TC;
+    col = TRANS ? e / 32 : e % TC;
+  };
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    int row, col;
+    rc(j * 256 + tid, row, col);
+    const long r = min(rt * 32 + row, R - 1), k = min(kb + col, K - 1);
+    v[j] = z[TRANS ? k * ld + r : r * ld + k];
+  }
+#pragma unroll
+  for (int j = 0; j < NL; ++j) {
+    int row, col;
+    rc(j * 256 + tid, row, col);
+    const float x = (rt * 32 + row < R && kb + col < K) ? v[j] * scale : 0.0f;
+    if constexpr (FE == 8) t[row][col] = from_f32<bf16>(x);
+    else t[row][col] = f32_to_e4m3(x);
+  }
+  __syncthreads();
+  const int KS = Kp / (2 * FE), ks0 = kb / (2 * FE);
+  for (int f = tid; f < NKS * 64; f += 256) {
+    const int g = f / 64, l = f % 64;
+    if (ks0 + g >= KS) break;   // (the last tile may reach past Kp, a multiple of 2 FE only)
+    const TD *src = &t[l & 31][g * 2 * FE + FE * (l >> 5)];
+    TD *dst = out + (((long)rt * KS + ks0 + g) * 64 + l) * FE;
+#pragma unroll
+    for (int q = 0; q < FE * (int)sizeof(TD) / 16; ++q)
+      reinterpret_cast<i32x4 *>(dst)[q] = reinterpret_cast<const i32x4 *>(src)[q];
+  }
 }
 hipError_t pack_frag_bf16(const float *z, long ld, int R, int K, int Rp, int Kp, bf16 *out, hipStream_t s) {
-  const long n = (long)Rp * Kp;
-  if (n > 0) pack_frag_kernel<bf16, 8><<<GRID1(n), 0, s>>>(z, ld, R, K, Rp, Kp, 1.0f, out);
+  if (Rp <= 0 || Kp <= 0) return hipSuccess;
+  if (R <= 0 || K <= 0) return hipErrorInvalidValue;
+  pack_frag_kernel<bf16, 8, false><<<dim3((Kp + 63) / 64, Rp / 32), 256, 0, s>>>(z, ld, R, K, Rp, Kp, 1.0f, out);
+  return hipGetLastError();
+}
+hipError_t pack_frag_bf16_t(const float *z, long ld, int R, int K, int Rp, int Kp, bf16 *out, hipStream_t s) {
+  if (Rp <= 0 || Kp <= 0) return hipSuccess;
+  if (R <= 0 || K <= 0) return hipErrorInvalidValue;
+  pack_frag_kernel<bf16, 8, true><<<dim3((Kp + 63) / 64, Rp / 32), 256, 0, s>>>(z, ld, R, K, Rp, Kp, 1.0f, out);
   return hipGetLastError();
 }
 hipError_t pack_frag_fp8(const float *z, long ld, int R, int K, int Rp, int Kp, float inv_scale, u8 *out,
                          hipStream_t s) {
-  const long n = (long)Rp * Kp;
-  if (n > 0) pack_frag_kernel<u8, 32><<<GRID1(n), 0, s>>>(z, ld, R, K, Rp, Kp, inv_scale, out);
+  if (Rp <= 0 || Kp <= 0) return hipSuccess;
+  if (R <= 0 || K <= 0) return hipErrorInvalidValue;
+  pack_frag_kernel<u8, 32, false><<<dim3((Kp + 63) / 64, Rp / 32), 256, 0, s>>>(z, ld, R, K, Rp, Kp, inv_scale, out);
   return hipGetLastError();
 }
 
@@ -378,6 +416,24 @@ hipError_t fc_wgrad_f32(const float *g, const float *y, long ldy, int B, int N, 
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   return gemm_nt_f32(gT, B, yT, B, dw, M, N, M, B, B % 16 == 0, s);
+}
+// BF16 networks: dW_fc = g^T y on the BF16 matrix cores, FP32 accumulation and output.  g^T
+// and y^T are packed straight into fragment order (rows p and m, k = the batch), then the
+// fragment GEMM runs with N as its rows and M as its columns.
+size_t fc_wgrad_bf16_scratch(int B, int N, int M) {
+  const size_t kp = ((size_t)B + 15) / 16 * 16;
+  return (((size_t)N + 31) / 32 * 32 * kp * 2 + 255) / 256 * 256 + ((size_t)M + 31) / 32 * 32 * kp * 2;
+}
+hipError_t fc_wgrad_bf16(const float *g, const float *y, long ldy, int B, int N, int M, float *dw, void *tmp,
+                         hipStream_t s) {
+  if ((long)N * M <= 0 || B <= 0) return hipSuccess;
+  const int Kp = (B + 15) / 16 * 16, Np = (N + 31) / 32 * 32, Mp = (M + 31) / 32 * 32;
+  bf16 *gp = static_cast<bf16 *>(tmp);
+  bf16 *yp = reinterpret_cast<bf16 *>(static_cast<char *>(tmp) + ((size_t)Np * Kp * 2 + 255) / 256 * 256);
+  hipError_t e = pack_frag_bf16_t(g, N, N, B, Np, Kp, gp, s);
+  if (e == hipSuccess) e = pack_frag_bf16_t(y, ldy, M, B, Mp, Kp, yp, s);
+  if (e == hipSuccess) e = gemm_frag_bf16_f32(gp, yp, dw, M, N, M, Kp / 16, s);
+  return e;
 }
 hipError_t fc_wgrad_f64(const double *g, const float *y, long ldy, int B, int N, int M, float *dw, hipStream_t s) {
   const long n = (long)N * M;

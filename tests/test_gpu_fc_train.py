@@ -67,24 +67,29 @@ def test_fc_gradient_matches_oracle(dsi, prec, shape):
     net.free()
 
 
-def test_fc_gradient_bf16_same_state(dsi):
+@pytest.mark.parametrize("shape", [(32, 32, 256, 4), (45, 50, 500, 37), (64, 64, 1024, 64)])
+def test_fc_gradient_bf16_same_state(dsi, shape):
+    """BF16 networks compute dW_fc on the BF16 matrix cores from packed dx~^T and y^T: pixel
+    and measurement counts that are not multiples of a 32-row tile and batches that are not
+    multiples of a 16-deep k-step exercise the packing tails and the GEMM's edges."""
     import torch
 
     import oracle
     P, ctx = dsi
-    case = make_case(32, 32, 256, 4, cfg_id=62, bias_std=0.05)
+    n1, n2, M, B = shape
+    case = make_case(n1, n2, M, B, cfg_id=62, bias_std=0.05)
     params = case.torch_params()
     net = _prepare(ctx, case, "bf16")
     y, B = _t(case.y), case.B
     xh, saved = net.forward_train(y)
     acts = [net.saved_activation(saved, B, l).cpu().numpy().astype(np.float64) for l in range(4)]
     g_out = (2.0 / B) * (xh.reshape(B, -1).cpu().numpy().astype(np.float64) - case.x)
-    g, _ = net.backward(_t(g_out).reshape(B, 32, 32), saved, params)
+    g, _ = net.backward(_t(g_out).reshape(B, n1, n2), saved, params)
     torch.cuda.synchronize()
     H = oracle.backward_acts(case.oracle_net(), case.phi.T, case.w, case.y,
                              [[acts[l][b] for l in range(4)] for b in range(B)], g_out, want_gwfc=True)
     e = _rel(g.w_fc.cpu().numpy(), H.wfc)
-    print(f"bf16 gW_fc same-state rel err {e:.2e}")
+    print(f"bf16 {shape} gW_fc same-state rel err {e:.2e}")
     assert e <= GTOL["bf16"]
     net.free()
 
