@@ -579,11 +579,18 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   const int a0 = px + 8 * h + OFF, odd = NCOPY == 2 ? (a0 & 1) : 0;
   const T *trow0 = tile + odd * COPY + wave * LWA + a0 - odd;
 
-  // 2-byte outputs: an image's four 16-byte stores per lane are issued during the next
-  // image's MFMAs (then the last image's after the loop), so the stores stream out
-  // between the matrix instructions instead of stalling the wave in a burst
-  constexpr bool PIPE = sizeof(TO) == 2;
-  i32x4 pend[2 * NCT];
+  // 2-byte outputs and FP8 codes: an image's 16-byte stores per lane (four for BF16, two
+  // for 64-channel FP8 pixels) are issued during the next image's MFMAs (then the last
+  // image's after the loop), so the stores stream out between the matrix instructions
+  // instead of stalling the wave in a burst; pend_off holds each one's element offset
+  constexpr bool FP8OUT = sizeof(TO) == 1 && NCT == 2 && EPI == EPI_BIAS;
+  constexpr bool PIPE = sizeof(TO) == 2 || FP8OUT;
+  constexpr int NPEND = FP8OUT ? 2 : 2 * NCT;
+  i32x4 pend[NPEND];
+  unsigned pend_off[NPEND];
+#pragma unroll
+  for (int j = 0; j < NPEND; ++j)
+    pend_off[j] = FP8OUT ? ooff[0][0] + 28 * h + 16 * j : ooff[j >> 1][2 * (j & 1)] + 4 * h;
   TO *pend_img = out;
   bool pend_live = false;
   for (int im = 0; im < nimg; ++im) {
@@ -629,9 +636,9 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         }
       }
       if constexpr (PIPE) {
-        if (u >= 1 && u <= 2 * NCT && pend_live) {
+        if (u >= 1 && u <= NPEND && pend_live) {
           const int j = u - 1;
-          *reinterpret_cast<i32x4 *>(pend_img + ooff[j >> 1][2 * (j & 1)] + 4 * h) = pend[j];
+          *reinterpret_cast<i32x4 *>(pend_img + pend_off[j]) = pend[j];
         }
         __builtin_amdgcn_sched_barrier(0);
       }
@@ -703,9 +710,9 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
         code[0][q] = (int)sw[0];
         code[1][q] = (int)sw[1];
       }
-      TO *dst = oimg + ooff[0][0] + 28 * h;   // channel 32h of the pixel (ooff[0][0] points at 4h)
-      *reinterpret_cast<i32x4 *>(dst) = i32x4{code[0][0], code[1][0], code[0][1], code[1][1]};
-      *reinterpret_cast<i32x4 *>(dst + 16) = i32x4{code[0][2], code[1][2], code[0][3], code[1][3]};
+      // channel 32h of the pixel (ooff[0][0] points at 4h), stored during the next image's MFMAs
+      pend[0] = i32x4{code[0][0], code[1][0], code[0][1], code[1][1]};
+      pend[1] = i32x4{code[0][2], code[1][2], code[0][3], code[1][3]};
       continue;
     }
 #pragma unroll
@@ -736,8 +743,7 @@ __global__ __launch_bounds__(256) void conv_first_kernel(const TI *__restrict__ 
   if constexpr (PIPE) {   // the last image's stores
     if (pend_live) {
 #pragma unroll
-      for (int j = 0; j < 2 * NCT; ++j)
-        *reinterpret_cast<i32x4 *>(pend_img + ooff[j >> 1][2 * (j & 1)] + 4 * h) = pend[j];
+      for (int j = 0; j < NPEND; ++j) *reinterpret_cast<i32x4 *>(pend_img + pend_off[j]) = pend[j];
     }
   }
 }
