@@ -619,22 +619,51 @@ hipError_t adam_f32(float *th, const float *g, float *m, float *v, long n, float
 }
 // Several tensors in one launch: tensor k owns the flat range [start[k], start[k+1]); its
 // updated values are also written to mirror (when given), the network's own copy.
-__global__ void adam_multi_kernel(AdamMulti a, float lr, float b1, float b2, float eps, float c1, float c2) {
-  long idx = (long)blockIdx.x * 256 + threadIdx.x;
+// A thread updates four consecutive elements of one segment (each segment's thread count is
+// rounded up, so a group never spans two): 16-byte loads and stores when the group is whole and
+// the segment's arrays are 16-byte aligned, element by element otherwise.  Every element takes
+// the same arithmetic either way.
+__global__ __launch_bounds__(256) void adam_multi_kernel(AdamMulti a, float lr, float b1, float b2, float eps,
+                                                         float c1, float c2) {
+  long q = (long)blockIdx.x * 256 + threadIdx.x;
   int k = 0;
-  while (k < a.nseg && idx >= a.seg[k].n) {
-    idx -= a.seg[k].n;
+  while (k < a.nseg && q >= (a.seg[k].n + 3) / 4) {
+    q -= (a.seg[k].n + 3) / 4;
     ++k;
   }
   if (k >= a.nseg) return;
   const AdamSeg &sg = a.seg[k];
-  const float t = adam_one(sg.th[idx], sg.g[idx], sg.m[idx], sg.v[idx], lr, b1, b2, eps, c1, c2);
-  if (sg.mirror) sg.mirror[idx] = t;
+  const long i0 = 4 * q;
+  const unsigned long al = reinterpret_cast<unsigned long>(sg.th) | reinterpret_cast<unsigned long>(sg.g) |
+                           reinterpret_cast<unsigned long>(sg.m) | reinterpret_cast<unsigned long>(sg.v) |
+                           reinterpret_cast<unsigned long>(sg.mirror);
+  if (i0 + 3 < sg.n && (al & 15) == 0) {
+    f32x4 th = *reinterpret_cast<const f32x4 *>(sg.th + i0), m = *reinterpret_cast<const f32x4 *>(sg.m + i0);
+    f32x4 v = *reinterpret_cast<const f32x4 *>(sg.v + i0);
+    const f32x4 g = *reinterpret_cast<const f32x4 *>(sg.g + i0);
+#pragma unroll
+    for (int e = 0; e < 4; ++e) {
+      float te = th[e], me = m[e], ve = v[e];
+      adam_one(te, g[e], me, ve, lr, b1, b2, eps, c1, c2);
+      th[e] = te;
+      m[e] = me;
+      v[e] = ve;
+    }
+    *reinterpret_cast<f32x4 *>(sg.th + i0) = th;
+    *reinterpret_cast<f32x4 *>(sg.m + i0) = m;
+    *reinterpret_cast<f32x4 *>(sg.v + i0) = v;
+    if (sg.mirror) *reinterpret_cast<f32x4 *>(sg.mirror + i0) = th;
+  } else {
+    for (long i = i0; i < i0 + 4 && i < sg.n; ++i) {
+      const float t = adam_one(sg.th[i], sg.g[i], sg.m[i], sg.v[i], lr, b1, b2, eps, c1, c2);
+      if (sg.mirror) sg.mirror[i] = t;
+    }
+  }
 }
 hipError_t adam_multi(const AdamMulti &a, float lr, float b1, float b2, float eps, float c1, float c2,
                       hipStream_t s) {
   long n = 0;
-  for (int k = 0; k < a.nseg; ++k) n += a.seg[k].n;
+  for (int k = 0; k < a.nseg; ++k) n += (a.seg[k].n + 3) / 4;
   if (n > 0) adam_multi_kernel<<<GRID1(n), 0, s>>>(a, lr, b1, b2, eps, c1, c2);
   return hipGetLastError();
 }
