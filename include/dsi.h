@@ -270,12 +270,19 @@ dsi_status dsi_metrics(dsi_ctx *ctx, const float *xhat, const float *x, int B, i
 /* ---------------------------------------------------- benchmarking */
 /* When enabled, every forward pass through the paper's network records HIP
  * events on the caller's stream at the boundaries of its stages {proxy GEMM,
- * conv layer 1, conv layer 2, conv layer 3}. */
+ * conv layer 1, conv layer 2, conv layer 3}: one before the pass's first kernel,
+ * one after each stage.  The events are timing-only (no system-scope fence), so
+ * recording them does not write the caches back between stages. */
 dsi_status dsi_set_stage_timing(dsi_ctx *ctx, int enable);
 /* Waits for the recorded events, writes the milliseconds spent in each of the
  * first `nstages` stages summed over the timed passes into ms (host array) and
  * their number into *calls (host), then forgets them. */
 dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls);
+/* The same per pass: ms (host array of max_passes * nstages) receives stage k of
+ * the p-th timed pass at ms[p * nstages + k] for p < min(*calls, max_passes)
+ * (zeros elsewhere); *calls (host) = the number of timed passes.  Forgets every
+ * recorded event, also those of passes beyond max_passes. */
+dsi_status dsi_stage_times_each(dsi_ctx *ctx, double *ms, int nstages, int max_passes, int *calls);
 
 #ifdef __cplusplus
 }

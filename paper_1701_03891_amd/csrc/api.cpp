@@ -101,8 +101,9 @@ struct StageClock {
   }
   void mark() {
     if (!set) return;
+    // timing only: no system-scope fence, so recording does not write back the L2 between stages
     hipEvent_t e;
-    if (hipEventCreate(&e) == hipSuccess) {
+    if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess) {
       (void)hipEventRecord(e, s);
       set->push_back(e);
     }
@@ -443,6 +444,8 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     return DSI_OK;
   }
   if (hidden_only) return hidden_impl(n, B, base, L, s);
+  StageClock clk(ctx, s);
+  clk.mark();
   // proxy x~ = W_fc y (K padded to Mpad with zeros)
   const bool direct_y = ((M % 16 == 0) && aligned16(y)) || n->prec == DSI_FP8_E4M3 || n->prec == DSI_BF16;
   const float *yk = y;
@@ -454,8 +457,6 @@ dsi_status forward_impl(dsi_ctx *ctx, const dsi_net *n, const float *y, float *x
     ldy = n->Mpad;
   }
   float *xout_last = (L.act[d.L] == SIZE_MAX) ? xhat : at<float>(base, L.act[d.L]);
-  StageClock clk(ctx, s);
-  clk.mark();
   if (n->path == PATH_GENERIC) {
     float *xt = at<float>(base, L.xt);
     HIPCHK(dsi::gemm_nt_f32(yk, ldy, (const float *)n->wfc, n->Mpad, xt, N, B, N, n->Mpad, true, s));
@@ -1234,24 +1235,44 @@ dsi_status dsi_set_stage_timing(dsi_ctx *ctx, int enable) {
   return DSI_OK;
 }
 
-dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls) {
-  if (!ctx || !ms || !calls) return fail(DSI_E_NULL, "ctx, ms and calls must be non-NULL");
-  if (nstages < 1) return fail(DSI_E_SHAPE, "nstages = %d", nstages);
-  for (int k = 0; k < nstages; ++k) ms[k] = 0.0;
+namespace {
+// Reads the recorded passes' stage times and forgets the events.  Pass p's stage k is added to
+// ms[k] (sum = true) or written to ms[p * nstages + k] for p < max_passes (sum = false).
+dsi_status read_stage_times(dsi_ctx *ctx, double *ms, int nstages, int max_passes, bool sum, int *calls) {
+  const long nout = sum ? nstages : (long)nstages * max_passes;
+  for (long k = 0; k < nout; ++k) ms[k] = 0.0;
   int n = 0;
+  dsi_status st = DSI_OK;
   for (auto &set : ctx->ev) {
     if (set.empty()) continue;
-    if (hipEventSynchronize(set.back()) != hipSuccess) return fail(DSI_E_HIP, "event synchronize failed");
-    for (size_t k = 0; k + 1 < set.size() && (int)k < nstages; ++k) {
-      float t = 0.0f;
-      if (hipEventElapsedTime(&t, set[k], set[k + 1]) == hipSuccess) ms[k] += t;
+    if (st == DSI_OK && hipEventSynchronize(set.back()) != hipSuccess)
+      st = fail(DSI_E_HIP, "event synchronize failed");
+    if (st == DSI_OK && (sum || n < max_passes)) {
+      double *row = sum ? ms : ms + (long)n * nstages;
+      for (size_t k = 0; k + 1 < set.size() && (int)k < nstages; ++k) {
+        float t = 0.0f;
+        if (hipEventElapsedTime(&t, set[k], set[k + 1]) == hipSuccess) row[k] += t;
+      }
     }
     for (hipEvent_t e : set) (void)hipEventDestroy(e);
     ++n;
   }
   ctx->ev.clear();
   *calls = n;
-  return DSI_OK;
+  return st;
+}
+}  // namespace
+
+dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls) {
+  if (!ctx || !ms || !calls) return fail(DSI_E_NULL, "ctx, ms and calls must be non-NULL");
+  if (nstages < 1) return fail(DSI_E_SHAPE, "nstages = %d", nstages);
+  return read_stage_times(ctx, ms, nstages, 0, true, calls);
+}
+
+dsi_status dsi_stage_times_each(dsi_ctx *ctx, double *ms, int nstages, int max_passes, int *calls) {
+  if (!ctx || !ms || !calls) return fail(DSI_E_NULL, "ctx, ms and calls must be non-NULL");
+  if (nstages < 1 || max_passes < 1) return fail(DSI_E_SHAPE, "nstages = %d, max_passes = %d", nstages, max_passes);
+  return read_stage_times(ctx, ms, nstages, max_passes, false, calls);
 }
 
 dsi_status dsi_saved_activation(dsi_ctx *ctx, const dsi_net *net, const void *saved, size_t saved_bytes, int B,

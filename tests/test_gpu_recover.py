@@ -217,3 +217,31 @@ def test_measure_noisy_parity(dsi):
     t = lambda a: torch.tensor(a, dtype=torch.float32, device="cuda")  # noqa: E731
     got = ctx.measure_noisy(t(phi), t(x), t(e), 20.0).cpu().numpy().astype(np.float64)
     assert relerr_per_image(got, ref).max() <= 1e-5
+
+
+@pytest.mark.parametrize("prec", ["bf16", "f32", "fp8"])
+def test_stage_timing_per_pass(dsi, prec):
+    """Stage timing records one set of events per forward pass and does not change the result:
+    the per-pass query returns the passes' four stage times, at most max_passes of them, and
+    forgets every recorded event."""
+    import torch
+
+    from paper_1701_03891_amd import _lib
+    P, ctx = dsi
+    case = make_case(32, 32, 256, 4, cfg_id=31, bias_std=0.05)
+    net = ctx.prepare(32, 32, 256, case.torch_params(), prec=prec)
+    y = torch.tensor(case.y, dtype=torch.float32, device="cuda")
+    ref = net.recover(y).clone()
+    _lib.dsi_stage_times(ctx.h)
+    _lib.dsi_set_stage_timing(ctx.h, 1)
+    outs = [net.recover(y) for _ in range(3)]
+    _lib.dsi_set_stage_timing(ctx.h, 0)
+    rows, calls = _lib.dsi_stage_times_each(ctx.h, 4, 2)
+    assert calls == 3 and len(rows) == 2
+    assert all(len(r) == 4 and all(t > 0 for t in r) for r in rows)
+    assert all(torch.equal(o, ref) for o in outs)
+    net.recover(y)
+    torch.cuda.synchronize()
+    assert _lib.dsi_stage_times_each(ctx.h, 4, 2) == ([], 0)
+    assert _lib.dsi_stage_times(ctx.h, 4)[1] == 0
+    net.free()
