@@ -77,9 +77,9 @@ def make_inputs(ctx, P, torch, cfg_id=2):
 
 def time_path(ctx, net, y, steps, warmup, torch):
     """Times `steps` recoveries of the batch y back to back.  The total comes from two events
-    around the loop; each pass's stage times and latency (its first kernel's start to its last
-    kernel's end) come from the timing-only events the library records between its stages,
-    which, unlike a default event per step, write no caches back."""
+    around the loop; each pass's stage times and the per-batch latencies (from one pass's first
+    stage event to the next pass's) come from the timing-only events the library records
+    between its stages, which, unlike a default event per step, write no caches back."""
     from paper_1701_03891_amd import _lib
     B = y.shape[0]
     xh = torch.empty((B, N1, N2), dtype=torch.float32, device=y.device)
@@ -103,7 +103,7 @@ def time_path(ctx, net, y, steps, warmup, torch):
     rows, calls = _lib.dsi_stage_times_each(ctx.h, 4, steps)
     assert calls == steps, f"{calls} timed passes recorded for {steps} steps"
     rows = np.array(rows)
-    per = rows.sum(axis=1)
+    per = rows[:-1, 4]
     stages = {name: float(rows[:, q].mean()) for q, name in
               enumerate(["proxy_gemm", "conv1", "conv2", "conv3"])}
     return dict(total_ms=total_ms, wall_s=wall, per_step_ms=per, stages=stages, xhat=xh)

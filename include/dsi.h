@@ -274,14 +274,21 @@ dsi_status dsi_metrics(dsi_ctx *ctx, const float *xhat, const float *x, int B, i
  * one after each stage.  The events are timing-only (no system-scope fence), so
  * recording them does not write the caches back between stages. */
 dsi_status dsi_set_stage_timing(dsi_ctx *ctx, int enable);
+/* The same for a subset of the stages: bit k of `stages` times stage k (bit 0 the
+ * proxy GEMM, bit k >= 1 conv layer k); only the boundaries of timed stages get an
+ * event, so fewer stages disturb the pass less.  0 turns timing off. */
+dsi_status dsi_set_stage_timing_mask(dsi_ctx *ctx, unsigned stages);
 /* Waits for the recorded events, writes the milliseconds spent in each of the
  * first `nstages` stages summed over the timed passes into ms (host array) and
  * their number into *calls (host), then forgets them. */
 dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls);
-/* The same per pass: ms (host array of max_passes * nstages) receives stage k of
- * the p-th timed pass at ms[p * nstages + k] for p < min(*calls, max_passes)
- * (zeros elsewhere); *calls (host) = the number of timed passes.  Forgets every
- * recorded event, also those of passes beyond max_passes. */
+/* The same per pass: ms (host array of max_passes * (nstages + 1)) receives, in
+ * row p = 0 .. min(*calls, max_passes) - 1 of nstages + 1 columns, stage k of the
+ * p-th timed pass at ms[p * (nstages + 1) + k] (0 for a stage not timed) and, in
+ * the last column, the time from that pass's first event to the next timed pass's
+ * first event (0 for the last pass).  Other entries are 0; *calls (host) = the
+ * number of timed passes.  Forgets every recorded event, also those of passes
+ * beyond max_passes. */
 dsi_status dsi_stage_times_each(dsi_ctx *ctx, double *ms, int nstages, int max_passes, int *calls);
 
 #ifdef __cplusplus

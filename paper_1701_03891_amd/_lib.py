@@ -29,7 +29,8 @@ EXPORTS = ["dsi_create", "dsi_destroy", "dsi_last_error", "dsi_version", "dsi_me
            "dsi_forward_train", "dsi_backward", "dsi_loss_grad", "dsi_train_step", "dsi_metrics",
            "dsi_set_stage_timing", "dsi_stage_times", "dsi_saved_activation", "dsi_net_calibrate",
            "dsi_net_get_scales", "dsi_measure_noisy", "dsi_recover_noalloc",
-           "dsi_set_recompute_budget", "dsi_set_workspace", "dsi_stage_times_each"]
+           "dsi_set_recompute_budget", "dsi_set_workspace", "dsi_stage_times_each",
+           "dsi_set_stage_timing_mask"]
 
 NOALLOC_SCRATCH_BYTES = 64 << 20     # DSI_NOALLOC_SCRATCH_BYTES
 
@@ -104,6 +105,7 @@ def lib() -> ctypes.CDLL:
         "dsi_net_get_scales": (st, [P, ctypes.POINTER(ctypes.c_float), i]),
         "dsi_stage_times": (st, [P, ctypes.POINTER(ctypes.c_double), i, ctypes.POINTER(ctypes.c_int)]),
         "dsi_stage_times_each": (st, [P, ctypes.POINTER(ctypes.c_double), i, i, ctypes.POINTER(ctypes.c_int)]),
+        "dsi_set_stage_timing_mask": (st, [P, ctypes.c_uint]),
     }
     for name, (res, args) in sig.items():
         f = getattr(L, name)
@@ -222,11 +224,18 @@ def dsi_stage_times(ctx, nstages=4):
     return list(arr), n.value
 
 
+def dsi_set_stage_timing_mask(ctx, stages):
+    call("dsi_set_stage_timing_mask", ctx, int(stages))
+
+
 def dsi_stage_times_each(ctx, nstages, max_passes):
-    arr = (ctypes.c_double * (nstages * max_passes))()
+    """(rows, calls): rows[p] = the p-th timed pass's nstages stage times followed by the time
+    from its first event to the next pass's first event."""
+    w = nstages + 1
+    arr = (ctypes.c_double * (w * max_passes))()
     n = ctypes.c_int()
     call("dsi_stage_times_each", ctx, arr, nstages, max_passes, ctypes.byref(n))
-    return [list(arr[p * nstages:(p + 1) * nstages]) for p in range(min(n.value, max_passes))], n.value
+    return [list(arr[p * w:(p + 1) * w]) for p in range(min(n.value, max_passes))], n.value
 
 
 def dsi_saved_activation(ctx, net, saved, saved_bytes, B, layer, out, stream):

@@ -82,30 +82,35 @@ struct dsi_ctx {
   bool ws_caller = false;    // ws is caller memory (dsi_set_workspace): never grown or freed here
   void *fixed_ws = nullptr;  // device address of the fixed workspace array (dsi_recover_noalloc)
   size_t rc_budget = 0;      // workspace bytes a recompute-mode chunk may use (0: whole batch)
-  // stage timing (benchmarking): one set of events per timed forward pass
-  int timing = 0;
-  std::vector<std::vector<hipEvent_t>> ev;
+  // stage timing (benchmarking): bit k records the two boundaries of stage k; one set of
+  // (boundary index, event) pairs per timed forward pass
+  unsigned timing = 0;
+  std::vector<std::vector<std::pair<int, hipEvent_t>>> ev;
 };
 
 namespace {
-// Records the boundary event of stage `k` of the current forward pass.
+// Records the stage boundaries of the current forward pass: boundary k precedes stage k and
+// follows stage k - 1; it gets an event when either of them is timed.
 struct StageClock {
   dsi_ctx *ctx;
   hipStream_t s;
-  std::vector<hipEvent_t> *set = nullptr;
+  std::vector<std::pair<int, hipEvent_t>> *set = nullptr;
+  int next = 0;
   StageClock(dsi_ctx *c, hipStream_t st) : ctx(c), s(st) {
     if (ctx && ctx->timing) {
       ctx->ev.emplace_back();
       set = &ctx->ev.back();
     }
   }
+  static bool timed(unsigned mask, int stage) { return stage >= 0 && stage < 32 && ((mask >> stage) & 1u); }
   void mark() {
-    if (!set) return;
+    const int k = next++;
+    if (!set || !(timed(ctx->timing, k) || timed(ctx->timing, k - 1))) return;
     // timing only: no system-scope fence, so recording does not write back the L2 between stages
     hipEvent_t e;
     if (hipEventCreateWithFlags(&e, hipEventDisableSystemFence) == hipSuccess) {
       (void)hipEventRecord(e, s);
-      set->push_back(e);
+      set->emplace_back(k, e);
     }
   }
 };
@@ -1231,37 +1236,54 @@ dsi_status dsi_backward(dsi_ctx *ctx, const dsi_net *net, const float *gxhat, co
 
 dsi_status dsi_set_stage_timing(dsi_ctx *ctx, int enable) {
   if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
-  ctx->timing = enable ? 1 : 0;
+  ctx->timing = enable ? ~0u : 0u;
   return DSI_OK;
 }
 
 namespace {
-// Reads the recorded passes' stage times and forgets the events.  Pass p's stage k is added to
-// ms[k] (sum = true) or written to ms[p * nstages + k] for p < max_passes (sum = false).
+// Reads the recorded passes' stage times and forgets the events.  sum: pass p's stage k is added
+// to ms[k].  Otherwise row p (p < max_passes) of ms, nstages + 1 wide, receives stage k at
+// column k and, in the last column, the time from the pass's first event to the next pass's
+// first event (0 for the last pass read, or when the two passes' first events differ).
 dsi_status read_stage_times(dsi_ctx *ctx, double *ms, int nstages, int max_passes, bool sum, int *calls) {
-  const long nout = sum ? nstages : (long)nstages * max_passes;
+  const int width = sum ? nstages : nstages + 1;
+  const long nout = sum ? nstages : (long)width * max_passes;
   for (long k = 0; k < nout; ++k) ms[k] = 0.0;
-  int n = 0;
+  std::vector<std::vector<std::pair<int, hipEvent_t>> *> sets;
+  for (auto &set : ctx->ev)
+    if (!set.empty()) sets.push_back(&set);
   dsi_status st = DSI_OK;
-  for (auto &set : ctx->ev) {
-    if (set.empty()) continue;
-    if (st == DSI_OK && hipEventSynchronize(set.back()) != hipSuccess)
+  for (auto *set : sets)
+    if (st == DSI_OK && hipEventSynchronize(set->back().second) != hipSuccess)
       st = fail(DSI_E_HIP, "event synchronize failed");
-    if (st == DSI_OK && (sum || n < max_passes)) {
-      double *row = sum ? ms : ms + (long)n * nstages;
-      for (size_t k = 0; k + 1 < set.size() && (int)k < nstages; ++k) {
-        float t = 0.0f;
-        if (hipEventElapsedTime(&t, set[k], set[k + 1]) == hipSuccess) row[k] += t;
-      }
+  const int n = (int)sets.size();
+  for (int p = 0; st == DSI_OK && p < n && (sum || p < max_passes); ++p) {
+    const auto &set = *sets[p];
+    double *row = sum ? ms : ms + (long)p * width;
+    for (size_t q = 0; q + 1 < set.size(); ++q) {
+      const int k = set[q].first;
+      float t = 0.0f;
+      if (set[q + 1].first == k + 1 && k < nstages && hipEventElapsedTime(&t, set[q].second, set[q + 1].second) == hipSuccess)
+        row[k] += t;
     }
-    for (hipEvent_t e : set) (void)hipEventDestroy(e);
-    ++n;
+    if (!sum && p + 1 < n && sets[p + 1]->front().first == set.front().first) {
+      float t = 0.0f;
+      if (hipEventElapsedTime(&t, set.front().second, sets[p + 1]->front().second) == hipSuccess) row[nstages] = t;
+    }
   }
+  for (auto &set : ctx->ev)
+    for (auto &e : set) (void)hipEventDestroy(e.second);
   ctx->ev.clear();
   *calls = n;
   return st;
 }
 }  // namespace
+
+dsi_status dsi_set_stage_timing_mask(dsi_ctx *ctx, unsigned stages) {
+  if (!ctx) return fail(DSI_E_NULL, "ctx is NULL");
+  ctx->timing = stages;
+  return DSI_OK;
+}
 
 dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls) {
   if (!ctx || !ms || !calls) return fail(DSI_E_NULL, "ctx, ms and calls must be non-NULL");

@@ -238,7 +238,17 @@ def test_stage_timing_per_pass(dsi, prec):
     _lib.dsi_set_stage_timing(ctx.h, 0)
     rows, calls = _lib.dsi_stage_times_each(ctx.h, 4, 2)
     assert calls == 3 and len(rows) == 2
-    assert all(len(r) == 4 and all(t > 0 for t in r) for r in rows)
+    # four stage times, then the time to the next pass's first event (not before this pass ends)
+    assert all(len(r) == 5 and all(t > 0 for t in r) and r[4] >= sum(r[:4]) - 1e-6 for r in rows)
+    assert all(torch.equal(o, ref) for o in outs)
+    # conv layer 2 alone: only its time and the period between passes
+    _lib.dsi_set_stage_timing_mask(ctx.h, 1 << 2)
+    outs = [net.recover(y) for _ in range(2)]
+    _lib.dsi_set_stage_timing_mask(ctx.h, 0)
+    rows, calls = _lib.dsi_stage_times_each(ctx.h, 4, 4)
+    assert calls == 2 and len(rows) == 2
+    assert rows[0][2] > 0 and rows[0][4] >= rows[0][2] and rows[1][2] > 0 and rows[1][4] == 0
+    assert rows[0][0] == rows[0][1] == rows[0][3] == 0 and rows[1][0] == rows[1][1] == rows[1][3] == 0
     assert all(torch.equal(o, ref) for o in outs)
     net.recover(y)
     torch.cuda.synchronize()
