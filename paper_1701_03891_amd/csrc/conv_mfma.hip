@@ -879,22 +879,34 @@ template <> DSI_INLINE void mma16<float>(const Frag8<float> &a, const Frag8<floa
 // of output rows r - u + 5 (11 rotating accumulators).  As output rows complete, the waves
 // put their Q tiles in LDS; every RG rows, after one barrier, a thread per output adds its
 // 11 shifted values and the bias (per-pixel biases staged in LDS once).
+// WHOLE (images at most 16 NWV columns wide): the block's 16 NWV input columns are the
+// whole image row, and it writes all of it.  The columns outside the image are zero, so
+// their Q is zero: it is not computed, the Q rows in LDS carry 5 zero columns on either
+// side instead, and no wave works on halo columns alone.
 // in [B][CIN/16][H][W][16]; wt [11 v][11 u][CIN]; out [B][H][W].
-template <int CIN, int NWV, int RB>
+template <int CIN, int NWV, int RB, bool WHOLE>
 __global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__restrict__ in,
                                                                   const bf16 *__restrict__ wt,
                                                                   const float *__restrict__ bias, int bias_pp,
                                                                   int relu, float *__restrict__ out, int H, int W,
                                                                   int col_tiles, int row_tiles) {
-  constexpr int NKS = CIN / 32, NIN = 16 * NWV, NOUT = NIN - 10, QS = 17, RG = 4;
+  constexpr int NKS = CIN / 32, NIN = 16 * NWV, QS = 17, RG = 4;
+  // Q columns held in LDS (index c: input column J0 - 5 + c) and output columns per block
+  constexpr int NQ = WHOLE ? NIN + 10 : NIN, NOUT = NQ - 10, QOFF = WHOLE ? 5 : 0;
   static_assert(RG * NOUT <= 64 * NWV, "one thread per output of a row group");
-  __shared__ float qs[2][RG][NIN * QS];
+  __shared__ float qs[2][RG][NQ * QS];
   __shared__ float bs[RB * NOUT];   // the block's per-pixel biases (loaded once)
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6, g = lane >> 4, n16 = lane & 15;
   const int rt = blockIdx.x % row_tiles, ct = (blockIdx.x / row_tiles) % col_tiles;
   const int b = blockIdx.x / (row_tiles * col_tiles);
   const int I0 = rt * RB, I1 = min(I0 + RB, H), J0 = ct * NOUT;
   const int NR = I1 - I0 + 10;   // input rows I0 - 5 .. I1 + 4
+  if constexpr (WHOLE) {   // the zero columns on either side (never written again)
+    for (int idx = tid; idx < 2 * RG * 10 * QS; idx += 64 * NWV) {
+      const int c = idx % (10 * QS), br = idx / (10 * QS);
+      qs[br / RG][br % RG][c < 5 * QS ? c : (NQ - 10) * QS + c] = 0.0f;
+    }
+  }
 
   // B operands: lane (v = n16, channel group g) holds W[32 ks + 8g + e][u][v], zero for v = 11..15
   Frag8<bf16> wf[11][NKS];
@@ -912,7 +924,7 @@ __global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__
   // take no branch, every row step issues the same loads, and the wait before a row's MFMAs
   // counts only the loads issued after it (a conditional load would make the compiler wait
   // for every load in flight once per pass over the ring).
-  const int jc = J0 - 5 + 16 * wave + n16;
+  const int jc = J0 - 5 + QOFF + 16 * wave + n16;
   constexpr unsigned OOB = 0x80000000u;
   const auto rsrc = __builtin_amdgcn_make_buffer_rsrc(const_cast<bf16 *>(in + (long)b * CIN * H * W), 0,
                                                       CIN * H * W * 2, 0x00020000);
@@ -968,7 +980,7 @@ __global__ __launch_bounds__(64 * NWV) void conv_last_rows_kernel(const bf16 *__
       float *q = qs[grp & 1][orow - grp * RG];
       // lane (v = n16, g) holds input columns 16 wave + 4g + e of tap column v
 #pragma unroll
-      for (int e = 0; e < 4; ++e) q[(16 * wave + 4 * g + e) * QS + n16] = acc[done][e];
+      for (int e = 0; e < 4; ++e) q[(QOFF + 16 * wave + 4 * g + e) * QS + n16] = acc[done][e];
       // every RG rows (and after the last) the threads add up the group's outputs
       if (orow - grp * RG == RG - 1 || t == NR - 1) {
         __syncthreads();
@@ -1066,13 +1078,23 @@ hipError_t conv_last(const T *in, const T *w, const float *bias, int bias_pp, in
                      int H, int W, hipStream_t s) {
   if (B <= 0) return hipSuccess;
   if constexpr (sizeof(T) == 2) {
-    // 5 waves: 80 input columns, 70 output columns per block; bands of 64 output rows
-    constexpr int NWV = 5, NOUT = 16 * NWV - 10, RB = 64;
+    // Images up to 64 (128) columns wide: 4 (8) waves over the whole row, one or two per
+    // SIMD, bands of 32 output rows (with 4 waves two blocks share a CU).  Wider: 5 waves
+    // over 80 input columns (70 outputs), bands of 64 rows.
+    const int RB = W <= 128 ? 32 : 64;
     if ((long)CIN * H * W * 2 >= (1L << 31)) return hipErrorInvalidValue;   // buffer offsets are 31-bit
-    const int col_tiles = (W + NOUT - 1) / NOUT, row_tiles = (H + RB - 1) / RB;
+    const int row_tiles = (H + RB - 1) / RB;
+    const int col_tiles = W <= 128 ? 1 : (W + 69) / 70;
     const long blocks = (long)B * col_tiles * row_tiles;
     if (blocks >= (1L << 31)) return hipErrorInvalidValue;
-    conv_last_rows_kernel<CIN, NWV, RB><<<(unsigned)blocks, 64 * NWV, 0, s>>>(in, w, bias, bias_pp, relu, out, H,
+    if (W <= 64)
+      conv_last_rows_kernel<CIN, 4, 32, true><<<(unsigned)blocks, 256, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W,
+                                                                            col_tiles, row_tiles);
+    else if (W <= 128)
+      conv_last_rows_kernel<CIN, 8, 32, true><<<(unsigned)blocks, 512, 0, s>>>(in, w, bias, bias_pp, relu, out, H, W,
+                                                                            col_tiles, row_tiles);
+    else
+      conv_last_rows_kernel<CIN, 5, 64, false><<<(unsigned)blocks, 320, 0, s>>>(in, w, bias, bias_pp, relu, out, H,
                                                                              W, col_tiles, row_tiles);
   } else {
     int tw, tpi;

@@ -101,12 +101,22 @@ def test_recover_width_not_multiple_of_8(dsi, prec):
 
 @pytest.mark.parametrize("bias_per_pixel", [True, False])
 def test_recover_conv3_row_bands_and_column_tiles(dsi, bias_per_pixel):
-    """70 x 152 images: BF16 conv3 works in 64-row bands of 70 output columns, so this
-    is a full and a 6-row band, and two full and one 12-column tile (each reading 5
-    columns beyond its edges); batch 2, M = 600."""
+    """70 x 152 images: BF16 conv3 works on images wider than 128 columns in 64-row bands of
+    70 output columns, so this is a full and a 6-row band, and two full and one 12-column
+    tile (each reading 5 columns beyond its edges); batch 2, M = 600."""
     P, ctx = dsi
     case = make_case(70, 152, 600, 2, cfg_id=13, bias_per_pixel=bias_per_pixel, bias_std=0.05)
     check_recovery(case, _recover(P, ctx, case, "bf16"), "bf16", label=f"70x152 bias_pp={bias_per_pixel}")
+
+
+@pytest.mark.parametrize("bias_per_pixel", [True, False])
+def test_recover_conv3_whole_rows_ragged_band(dsi, bias_per_pixel):
+    """100 x 90 images: BF16 conv3 gives images up to 128 columns wide 8 waves over the whole
+    row (here 90 columns and 38 past the edge) in 32-row bands, so this is three full bands
+    and a 4-row one; batch 3, M = 900."""
+    P, ctx = dsi
+    case = make_case(100, 90, 900, 3, cfg_id=15, bias_per_pixel=bias_per_pixel, bias_std=0.05)
+    check_recovery(case, _recover(P, ctx, case, "bf16"), "bf16", label=f"100x90 bias_pp={bias_per_pixel}")
 
 
 def test_recover_uneven_tiles_per_block(dsi):
