@@ -434,8 +434,9 @@ def cpu_baseline(phi, x, prm, y_host, xhs, n_img, c4=None, c1=None):
 
 
 def profile_leg(ctx, P, torch, leg, steps, warmup):
-    """One workload and precision alone (for rocprofv3 runs): prepare, warmup + steps
-    recoveries of one batch, each stage's time from the library's HIP events."""
+    """One workload and precision alone (for rocprofv3 runs): prepare, SETTLE_S seconds of
+    recoveries while the clock ramps up, then warmup + steps recoveries of one batch, each
+    stage's time from the library's HIP events."""
     import synth
     cfg, prec = leg.split(":")
     if cfg == "train":
@@ -444,7 +445,8 @@ def profile_leg(ctx, P, torch, leg, steps, warmup):
         prm = synth.he_init(synth.PAPER_ARCH, N1, N2, bias_per_pixel=True, cfg_id=3)
         t = lambda a: torch.tensor(np.ascontiguousarray(a), dtype=torch.float32, device="cuda:0")  # noqa: E731
         params = P.NetParams(t(phi.T), [t(w) for w in prm.w], [t(b) for b in prm.b])
-        st = train_network(ctx, P, torch, phi, params, warmup + steps, batch=128, pool=1024)
+        # 125 more steps first (~0.1 s) while the clock ramps up
+        st = train_network(ctx, P, torch, phi, params, 125 + warmup + steps, batch=128, pool=1024)
         print(json.dumps({"profile_leg": leg, "training": st}))
         return
     if cfg == "c2":
@@ -466,6 +468,11 @@ def profile_leg(ctx, P, torch, leg, steps, warmup):
         net.calibrate(ctx.measure(t(phi), t(xc)))
     net.reserve(B)
     xh = torch.empty((B, n, n), dtype=torch.float32, device=dev)
+    t_settle = time.perf_counter()   # recoveries while the clock ramps up
+    while time.perf_counter() - t_settle < SETTLE_S:
+        for _ in range(8):
+            net.recover(y, xh)
+        torch.cuda.synchronize()
     for _ in range(warmup):
         net.recover(y, xh)
     torch.cuda.synchronize()
