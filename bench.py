@@ -136,10 +136,16 @@ def time_path(ctx, net, y, steps, warmup, torch):
                 settle_passes=settle)
 
 
-def time_recover(net, y, n1, n2, steps, warmup, torch):
-    """Average ms per dsi_recover of the batch y (events on the current stream)."""
+def time_recover(net, y, n1, n2, steps, warmup, torch, settle_s=SETTLE_S):
+    """Average ms per dsi_recover of the batch y (events on the current stream), after
+    settle_s seconds of recoveries while the clock ramps up and `warmup` more."""
     B = y.shape[0]
     xh = torch.empty((B, n1, n2), dtype=torch.float32, device=y.device)
+    t_settle = time.perf_counter()
+    while time.perf_counter() - t_settle < settle_s:
+        for _ in range(8):
+            net.recover(y, xh)
+        torch.cuda.synchronize()
     for _ in range(warmup):
         net.recover(y, xh)
     torch.cuda.synchronize()
