@@ -524,7 +524,7 @@ def main():
                     help="first run one plain device copy of this many MiB (calibrates HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build runs on one GPU; --gpus {args.gpus} is not supported "
+        print(f"bench.py: the library and this benchmark run on one GPU; --gpus {args.gpus} is not supported "
               "(images are independent, so N GPUs would each run this benchmark on their own batch)",
               file=sys.stderr)
         sys.exit(2)
