@@ -218,22 +218,23 @@ __global__ __launch_bounds__(64 * WAVES) void conv_mid_kernel(const T *__restric
   if (has_next) tile_at(tl + G, nimg, ni0, nj0);
 
   // With prefetched staging the accumulators start from the bias, so the epilogue
-  // issues no loads.
+  // issues no loads.  Every bias load is unconditional, so all of them are in flight
+  // together (a load under a branch makes the compiler wait for it before the next):
+  // a pixel outside the image reads pixel 0's biases, and its outputs are never stored.
   constexpr bool PREBIAS = ASYNC && EPI == EPI_BIAS;
   f32x16 acc[ROWS][NCT];
 #pragma unroll
   for (int i = 0; i < ROWS; ++i) {
     const int gi = bi0 + wave * ROWS + i, gj = bj0 + px;
-    const bool live = gi < H && gj < W;
+    const long pix = gi < H && gj < W ? (long)gi * W + gj : 0;
 #pragma unroll
     for (int c = 0; c < NCT; ++c)
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
         f32x4 b4 = {0.0f, 0.0f, 0.0f, 0.0f};
-        if (PREBIAS && live) {
-          if (bias_pp) b4 = *reinterpret_cast<const f32x4 *>(bias + ((long)gi * W + gj) * COUT + c * 32 + h * 16 + q * 4);
-          else b4 = *reinterpret_cast<const f32x4 *>(bias + c * 32 + 8 * q + 4 * h);
-        }
+        if constexpr (PREBIAS)
+          b4 = *reinterpret_cast<const f32x4 *>(bias + (bias_pp ? pix * COUT + c * 32 + h * 16 + q * 4
+                                                                : (long)(c * 32 + 8 * q + 4 * h)));
 #pragma unroll
         for (int e = 0; e < 4; ++e) acc[i][c][4 * q + e] = b4[e];
       }
