@@ -121,7 +121,7 @@ def time_path(ctx, net, y, steps, warmup, torch):
     rows, calls = _lib.dsi_stage_times_each(ctx.h, 4, steps)
     assert calls == steps, f"{calls} timed passes recorded for {steps} steps"
     rows = np.array(rows)
-    per = rows[:-1, 4]
+    per = rows[:-1, 4] if steps > 1 else np.array([total_ms])   # one step: its own time
     conv2_ms = float(rows[:, 2].mean())
     # the breakdown: every stage timed, outside the timed region
     _lib.dsi_set_stage_timing(ctx.h, 1)
