@@ -288,7 +288,10 @@ dsi_status dsi_stage_times(dsi_ctx *ctx, double *ms, int nstages, int *calls);
  * the last column, the time from that pass's first event to the next timed pass's
  * first event (0 for the last pass).  Other entries are 0; *calls (host) = the
  * number of timed passes.  Forgets every recorded event, also those of passes
- * beyond max_passes. */
+ * beyond max_passes.
+ * Errors (these timing calls): DSI_E_NULL for a NULL ctx, ms or calls; DSI_E_SHAPE
+ * for nstages < 1 or max_passes < 1; DSI_E_HIP when an event cannot be waited for
+ * (the events are forgotten all the same). */
 dsi_status dsi_stage_times_each(dsi_ctx *ctx, double *ms, int nstages, int max_passes, int *calls);
 
 #ifdef __cplusplus
